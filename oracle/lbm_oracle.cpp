@@ -1,0 +1,527 @@
+// Plain, slow FP64 CPU oracle of the well-balanced phase-field lattice
+// Boltzmann step (Ju, Liu, Yan, Bao, Sun, Guo; arXiv 2311.10827).
+//
+// TEST INFRASTRUCTURE ONLY.  Nothing in the product path may include, link,
+// load or call this file; only the test-suite, the smoke check and the CPU
+// baseline leg of the benchmark use it.  It shares no code, header, table or
+// constant with the HIP library: every lattice table and every formula below
+// is restated here from the paper.
+//
+// The method is an iteration, so the oracle takes the algorithm's steps in
+// the paper's order and notation, one full-grid pass per step, with no
+// fusion or blocking:
+//   1. order parameter phi = sum_i f_i                      (Sec. 2.3.1, eq. order-parameter)
+//   2. density and viscosity, linear in phi                 (Sec. 2.3.2, eq. vis and the sentence before it)
+//   3. chemical potential mu = psi'(phi) - kappa lap(phi)   (Sec. 2.1, eq. chemical_potencial; Sec. 2.3.2, eq. Laplace)
+//   4. isotropic gradients of phi, mu and rho               (Sec. 2.3.2, eq. gradient)
+//   5. force F = -phi grad(mu) + G                          (Sec. 2.1 after eq. 6; Sec. 2.3.2 after eq. GGi)
+//   6. velocity rho u = sum_i c_i g_i + F/2                 (Sec. 2.3.2, macroscopic subequations)
+//   7. pressure p                                           (same)
+//   8. convection source S = u . grad(phi)                  (Sec. 2.3.1, eq. F_i)
+//   9. CH collision with source and its time derivative     (Sec. 2.3.1, eqs. BGK, H_i, F_i)
+//  10. NS collision with forcing                            (Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi)
+//  11. streaming (periodic, or half-way bounce-back walls)
+//  12. keep S for the next step's time derivative of F_i
+//
+// Readings where the paper is silent or garbled (listed in the design doc):
+//  * c_s^2 = 1/3, delta_x = delta_t = 1 (the text's "c/sqrt(3)" is garbled).
+//  * The time derivative in eq. BGK is the first-order backward difference
+//    [F_i(t) - F_i(t-1)]/delta_t, which needs S of the previous step.
+//  * rho(phi) and nu(phi) are linear between (phi_B, rho_B|nu_B) and
+//    (phi_A, rho_A|nu_A); tau_g = 1/2 + nu/c_s^2 per cell (Sec. 2.3.2).
+//  * tau_f = 1/2 + M/(c_s^2 alpha) (Sec. 2.3.1, eq. mobility).
+//  * Walls: half-way bounce-back for f and g; ghost values of phi and mu
+//    across a wall mirror the adjacent cell (the paper's tests are periodic).
+//  * Initial state: f = f^eq(phi0, mu(phi0)), g = g^eq(p=0, u0), and the
+//    previous-step source equals S computed from that state.
+//
+// The scalar type is a template parameter.  With R = double this is the
+// oracle; with R = Dual (value + one tangent) the same code, unchanged, is
+// the forward-mode tangent-linear model used to check the hand-written
+// adjoint: each arithmetic operation carries its exact derivative.
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <cstdlib>
+#include <vector>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+namespace {
+
+// ---------------------------------------------------------------- dual numbers
+struct Dual {
+  double v, d;
+  Dual() : v(0), d(0) {}
+  Dual(double a) : v(a), d(0) {}
+  Dual(double a, double b) : v(a), d(b) {}
+};
+inline Dual operator+(Dual a, Dual b) { return Dual(a.v + b.v, a.d + b.d); }
+inline Dual operator-(Dual a, Dual b) { return Dual(a.v - b.v, a.d - b.d); }
+inline Dual operator-(Dual a) { return Dual(-a.v, -a.d); }
+inline Dual operator*(Dual a, Dual b) { return Dual(a.v * b.v, a.d * b.v + a.v * b.d); }
+inline Dual operator/(Dual a, Dual b) {
+  double q = a.v / b.v;
+  return Dual(q, (a.d - q * b.d) / b.v);
+}
+inline Dual operator+(Dual a, double b) { return Dual(a.v + b, a.d); }
+inline Dual operator+(double a, Dual b) { return Dual(a + b.v, b.d); }
+inline Dual operator-(Dual a, double b) { return Dual(a.v - b, a.d); }
+inline Dual operator-(double a, Dual b) { return Dual(a - b.v, -b.d); }
+inline Dual operator*(Dual a, double b) { return Dual(a.v * b, a.d * b); }
+inline Dual operator*(double a, Dual b) { return Dual(a * b.v, a * b.d); }
+inline Dual operator/(Dual a, double b) { return Dual(a.v / b, a.d / b); }
+inline Dual operator/(double a, Dual b) {
+  double q = a / b.v;
+  return Dual(q, -q * b.d / b.v);
+}
+inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
+inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
+inline double val(double a) { return a; }
+inline double val(Dual a) { return a.v; }
+
+// ------------------------------------------------------------- D2Q9 lattice
+// Sec. 2.2, eq. eq:ci and the weights stated just after it.  Order used on
+// every interface of this project: 0 rest; 1 (+1,0); 2 (0,+1); 3 (-1,0);
+// 4 (0,-1); 5 (+1,+1); 6 (-1,+1); 7 (-1,-1); 8 (+1,-1).
+const int Q = 9;
+const int CX[Q] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+const double WT[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
+                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
+const double CS2 = 1.0 / 3.0;  // c_s^2 with c = 1
+int opposite(int i) {
+  for (int j = 0; j < Q; ++j)
+    if (CX[j] == -CX[i] && CY[j] == -CY[i]) return j;
+  return -1;
+}
+
+}  // namespace
+
+extern "C" {
+
+// Boundary kinds.
+enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
+
+typedef struct {
+  int32_t nx, ny;
+  int32_t bc_x, bc_y;
+  double phi_A, phi_B;  // paper phi_l, phi_v
+  double rho_A, rho_B;
+  double nu_A, nu_B;
+  double kappa, beta;
+  double M, alpha;      // tau_f = 1/2 + M/(c_s^2 alpha)
+  double gx, gy;        // body force G
+} orc_params;
+
+}  // extern "C"
+
+namespace {
+
+template <class R>
+struct Theta {       // the differentiable parameters
+  R kappa, beta, alpha, tau_f, nu_A, nu_B;
+};
+
+template <class R>
+struct Sim {
+  orc_params p;
+  Theta<R> th;
+  int nx, ny;
+  std::vector<R> f, g, Sp;     // pre-collision populations [9][ny][nx], S of previous step
+  // per-step work fields
+  std::vector<R> phi, rho, nu, mu, gphx, gphy, gmux, gmuy, grhx, grhy, Fx, Fy, ux, uy, pr, S;
+  std::vector<R> fs, gs;       // post-collision populations
+
+  explicit Sim(const orc_params& q) : p(q), nx(q.nx), ny(q.ny) {
+    th.kappa = q.kappa;
+    th.beta = q.beta;
+    th.alpha = q.alpha;
+    th.tau_f = 0.5 + q.M / (CS2 * q.alpha);  // eq. mobility solved for tau_f
+    th.nu_A = q.nu_A;
+    th.nu_B = q.nu_B;
+    size_t n = (size_t)nx * ny;
+    f.assign(Q * n, R(0)); g.assign(Q * n, R(0)); Sp.assign(n, R(0));
+    fs.assign(Q * n, R(0)); gs.assign(Q * n, R(0));
+    for (auto* v : {&phi, &rho, &nu, &mu, &gphx, &gphy, &gmux, &gmuy, &grhx, &grhy,
+                    &Fx, &Fy, &ux, &uy, &pr, &S})
+      v->assign(n, R(0));
+  }
+  size_t cells() const { return (size_t)nx * ny; }
+  size_t at(int x, int y) const { return (size_t)y * nx + x; }
+
+  // Index of the neighbour value used by the finite-difference stencils:
+  // periodic wrap, or the mirrored adjacent cell across a wall.
+  int sx(int x) const {
+    if (p.bc_x == ORC_PERIODIC) return ((x % nx) + nx) % nx;
+    return x < 0 ? 0 : (x >= nx ? nx - 1 : x);
+  }
+  int sy(int y) const {
+    if (p.bc_y == ORC_PERIODIC) return ((y % ny) + ny) % ny;
+    return y < 0 ? 0 : (y >= ny ? ny - 1 : y);
+  }
+
+  // Sec. 2.3.2, eq. gradient: grad Psi = sum_{i!=0} w_i c_i Psi(x+c_i) / c_s^2.
+  void gradient(const std::vector<R>& psi, std::vector<R>& gx, std::vector<R>& gy) const {
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        R ax = 0.0, ay = 0.0;
+        for (int i = 1; i < Q; ++i) {
+          R v = psi[at(sx(x + CX[i]), sy(y + CY[i]))];
+          ax += WT[i] * CX[i] * v / CS2;
+          ay += WT[i] * CY[i] * v / CS2;
+        }
+        gx[at(x, y)] = ax;
+        gy[at(x, y)] = ay;
+      }
+  }
+
+  // Sec. 2.3.2, eq. Laplace: lap Psi = sum_{i!=0} 2 w_i [Psi(x+c_i) - Psi(x)] / c_s^2.
+  void laplacian(const std::vector<R>& psi, std::vector<R>& out) const {
+#pragma omp parallel for schedule(static)
+    for (int y = 0; y < ny; ++y)
+      for (int x = 0; x < nx; ++x) {
+        R c = psi[at(x, y)];
+        R a = 0.0;
+        for (int i = 1; i < Q; ++i)
+          a += 2.0 * WT[i] * (psi[at(sx(x + CX[i]), sy(y + CY[i]))] - c) / CS2;
+        out[at(x, y)] = a;
+      }
+  }
+
+  // Sec. 2.1, eq. chemical_potencial, with the discrete Laplacian above.
+  void chemical_potential(const std::vector<R>& ph, std::vector<R>& out) const {
+    std::vector<R> lap(cells());
+    laplacian(ph, lap);
+    const double pl = p.phi_A, pv = p.phi_B, pm = 0.5 * (p.phi_A + p.phi_B);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < (long)cells(); ++k)
+      out[k] = 4.0 * th.beta * (ph[k] - pl) * (ph[k] - pv) * (ph[k] - pm) - th.kappa * lap[k];
+  }
+
+  // Linear density and viscosity in phi (Sec. 2.3.2, eq. vis and the text before it).
+  R density(R ph) const {
+    return p.rho_B + (ph - p.phi_B) * (p.rho_A - p.rho_B) / (p.phi_A - p.phi_B);
+  }
+  R viscosity(R ph) const {
+    return th.nu_B + (ph - p.phi_B) * (th.nu_A - th.nu_B) / (p.phi_A - p.phi_B);
+  }
+
+  // Sec. 2.3.1, eq. H_i.
+  void feq(R ph, R m, R* out) const {
+    for (int i = 0; i < Q; ++i)
+      out[i] = (i == 0) ? ph - (1.0 - WT[0]) * th.alpha * m : WT[i] * th.alpha * m;
+  }
+  // Sec. 2.3.1, eq. F_i, for a given value of u . grad(phi).
+  void source(R s, R* out) const {
+    for (int i = 0; i < Q; ++i) {
+      // I : (c_i c_i - c_s^2 I) = |c_i|^2 - 2 c_s^2 in two dimensions
+      double contraction = (double)(CX[i] * CX[i] + CY[i] * CY[i]) - 2.0 * CS2;
+      out[i] = WT[i] * s * (-1.0 + contraction / (2.0 * CS2));
+    }
+  }
+  // Sec. 2.3.2, eq. Siu.
+  R s_i(int i, R vx, R vy) const {
+    R cu = CX[i] * vx + CY[i] * vy;
+    R uu = vx * vx + vy * vy;
+    return WT[i] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+  }
+  // Sec. 2.3.2, eq. G_i.
+  void geq(R pp, R rh, R vx, R vy, R* out) const {
+    for (int i = 0; i < Q; ++i)
+      out[i] = (i == 0 ? pp / CS2 * (WT[0] - 1.0) : pp / CS2 * WT[i]) + rh * s_i(i, vx, vy);
+  }
+  // Sec. 2.3.2, eq. GGi (reading of the unbalanced parenthesis: the third
+  // term is the dyad u grad(rho) contracted with c_i c_i - c_s^2 I, over c_s^2).
+  void forcing(R tau, R vx, R vy, R fx, R fy, R rx, R ry, R* out) const {
+    R ugr = vx * rx + vy * ry;
+    for (int i = 0; i < Q; ++i) {
+      R cF = CX[i] * fx + CY[i] * fy;
+      // (u grad rho) : (c c - c_s^2 I) = sum_ab u_a d_b rho (c_a c_b - c_s^2 delta_ab)
+      R dyad = vx * rx * (CX[i] * CX[i] - CS2) + vx * ry * (CX[i] * CY[i]) +
+               vy * rx * (CY[i] * CX[i]) + vy * ry * (CY[i] * CY[i] - CS2);
+      out[i] = (1.0 - 1.0 / (2.0 * tau)) * WT[i] * (ugr + cF / CS2 + dyad / CS2);
+    }
+  }
+  // Sec. 2.3.2, macroscopic subequations: u and p from g, rho, F, grad(rho).
+  void macro(const R* gi, R rh, R fx, R fy, R rx, R ry, R& vx, R& vy, R& pp) const {
+    R mx = 0.0, my = 0.0, sum_nz = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      mx += CX[i] * gi[i];
+      my += CY[i] * gi[i];
+      if (i != 0) sum_nz += gi[i];
+    }
+    vx = (mx + 0.5 * fx) / rh;
+    vy = (my + 0.5 * fy) / rh;
+    pp = CS2 / (1.0 - WT[0]) * (sum_nz + 0.5 * (vx * rx + vy * ry) + rh * s_i(0, vx, vy));
+  }
+
+  // Steps 1-8 on the current pre-collision state.
+  void compute_macro() {
+    const size_t n = cells();
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < (long)n; ++k) {
+      R s = 0.0;
+      for (int i = 0; i < Q; ++i) s += f[i * n + k];
+      phi[k] = s;
+      rho[k] = density(s);
+      nu[k] = viscosity(s);
+    }
+    chemical_potential(phi, mu);
+    gradient(phi, gphx, gphy);
+    gradient(mu, gmux, gmuy);
+    gradient(rho, grhx, grhy);
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < (long)n; ++k) {
+      Fx[k] = -phi[k] * gmux[k] + p.gx;
+      Fy[k] = -phi[k] * gmuy[k] + p.gy;
+      R gi[Q];
+      for (int i = 0; i < Q; ++i) gi[i] = g[i * n + k];
+      macro(gi, rho[k], Fx[k], Fy[k], grhx[k], grhy[k], ux[k], uy[k], pr[k]);
+      S[k] = ux[k] * gphx[k] + uy[k] * gphy[k];
+    }
+  }
+
+  // Steps 9-10.
+  void collide() {
+    const size_t n = cells();
+#pragma omp parallel for schedule(static)
+    for (long k = 0; k < (long)n; ++k) {
+      R eq[Q], Fn[Q], Fo[Q], ge[Q], Gi[Q];
+      feq(phi[k], mu[k], eq);
+      source(S[k], Fn);
+      source(Sp[k], Fo);
+      for (int i = 0; i < Q; ++i) {
+        R fi = f[i * n + k];
+        // eq. BGK with delta_t = 1 and dF/dt ~ F(t) - F(t-1)
+        fs[i * n + k] = fi - (fi - eq[i]) / th.tau_f + Fn[i] + 0.5 * (Fn[i] - Fo[i]);
+      }
+      R tau_g = 0.5 + nu[k] / CS2;  // viscosity-relaxation relation, solved for tau_g
+      geq(pr[k], rho[k], ux[k], uy[k], ge);
+      forcing(tau_g, ux[k], uy[k], Fx[k], Fy[k], grhx[k], grhy[k], Gi);
+      for (int i = 0; i < Q; ++i) {
+        R gi = g[i * n + k];
+        gs[i * n + k] = gi - (gi - ge[i]) / tau_g + Gi[i];  // eq. BGK-NS
+      }
+    }
+  }
+
+  // Step 11: f_i(x + c_i, t+1) = f*_i(x, t); a link that crosses a wall
+  // returns to its own cell in the opposite direction.
+  void stream() {
+    const size_t n = cells();
+    for (int i = 0; i < Q; ++i) {
+      const int o = opposite(i);
+#pragma omp parallel for schedule(static)
+      for (int y = 0; y < ny; ++y)
+        for (int x = 0; x < nx; ++x) {
+          int xx = x + CX[i], yy = y + CY[i];
+          bool solid = (p.bc_x == ORC_WALL && (xx < 0 || xx >= nx)) ||
+                       (p.bc_y == ORC_WALL && (yy < 0 || yy >= ny));
+          size_t src = i * n + at(x, y);
+          if (solid) {
+            f[o * n + at(x, y)] = fs[src];
+            g[o * n + at(x, y)] = gs[src];
+          } else {
+            size_t dst = i * n + at(((xx % nx) + nx) % nx, ((yy % ny) + ny) % ny);
+            f[dst] = fs[src];
+            g[dst] = gs[src];
+          }
+        }
+    }
+  }
+
+  void step() {
+    compute_macro();
+    collide();
+    stream();
+    Sp = S;  // step 12
+  }
+
+  void init(const R* phi0, const R* u0x, const R* u0y) {
+    const size_t n = cells();
+    std::vector<R> ph(phi0, phi0 + n), m(n);
+    chemical_potential(ph, m);
+    for (size_t k = 0; k < n; ++k) {
+      R eq[Q], ge[Q];
+      feq(ph[k], m[k], eq);
+      R vx = u0x ? u0x[k] : R(0.0), vy = u0y ? u0y[k] : R(0.0);
+      geq(R(0.0), density(ph[k]), vx, vy, ge);
+      for (int i = 0; i < Q; ++i) {
+        f[i * n + k] = eq[i];
+        g[i * n + k] = ge[i];
+      }
+    }
+    compute_macro();
+    Sp = S;
+  }
+};
+
+template <class R>
+Sim<R>* sim_of(void* h) { return static_cast<Sim<R>*>(h); }
+
+template <class T>
+void copy_out(const std::vector<T>& v, double* dst) {
+  if (dst)
+    for (size_t k = 0; k < v.size(); ++k) dst[k] = val(v[k]);
+}
+
+}  // namespace
+
+extern "C" {
+
+// ------------------------------------------------------------ lattice tables
+void orc_lattice(int32_t* cx, int32_t* cy, double* w, double* cs2) {
+  for (int i = 0; i < Q; ++i) { cx[i] = CX[i]; cy[i] = CY[i]; w[i] = WT[i]; }
+  *cs2 = CS2;
+}
+
+void orc_set_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
+int orc_get_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
+
+// -------------------------------------------------------- local definitions
+// Single-cell forms, exposed so their moments can be checked against the
+// moment identities the paper states (Sec. 2.3.1, eq. sumfeqandF).
+void orc_feq(const orc_params* p, double phi, double mu, double* out) {
+  Sim<double> s(*p); s.feq(phi, mu, out);
+}
+void orc_source(const orc_params* p, double S, double* out) {
+  Sim<double> s(*p); s.source(S, out);
+}
+void orc_geq(const orc_params* p, double pr, double rho, double ux, double uy, double* out) {
+  Sim<double> s(*p); s.geq(pr, rho, ux, uy, out);
+}
+void orc_forcing(const orc_params* p, double tau, double ux, double uy, double Fx, double Fy,
+                 double rx, double ry, double* out) {
+  Sim<double> s(*p); s.forcing(tau, ux, uy, Fx, Fy, rx, ry, out);
+}
+void orc_macro(const orc_params* p, const double* g9, double rho, double Fx, double Fy,
+               double rx, double ry, double* ux, double* uy, double* pr) {
+  Sim<double> s(*p); s.macro(g9, rho, Fx, Fy, rx, ry, *ux, *uy, *pr);
+}
+// Discrete operators on a full field with the project's boundary rule.
+void orc_gradient(const orc_params* p, const double* field, double* gx, double* gy) {
+  Sim<double> s(*p);
+  std::vector<double> v(field, field + s.cells()), ax(s.cells()), ay(s.cells());
+  s.gradient(v, ax, ay);
+  copy_out(ax, gx); copy_out(ay, gy);
+}
+void orc_laplacian(const orc_params* p, const double* field, double* out) {
+  Sim<double> s(*p);
+  std::vector<double> v(field, field + s.cells()), o(s.cells());
+  s.laplacian(v, o);
+  copy_out(o, out);
+}
+void orc_chemical_potential(const orc_params* p, const double* phi, double* out) {
+  Sim<double> s(*p);
+  std::vector<double> v(phi, phi + s.cells()), o(s.cells());
+  s.chemical_potential(v, o);
+  copy_out(o, out);
+}
+double orc_tau_f(const orc_params* p) { return 0.5 + p->M / (CS2 * p->alpha); }
+
+// ------------------------------------------------------------- simulation
+void* orc_create(const orc_params* p) { return new Sim<double>(*p); }
+void orc_destroy(void* h) { delete sim_of<double>(h); }
+void orc_init(void* h, const double* phi0, const double* u0x, const double* u0y) {
+  sim_of<double>(h)->init(phi0, u0x, u0y);
+}
+void orc_step(void* h, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) sim_of<double>(h)->step();
+}
+// Moments of the current pre-collision state (steps 1-8, no collision).
+void orc_moments(void* h, double* phi, double* mu, double* ux, double* uy, double* pr,
+                 double* rho, double* S) {
+  Sim<double>* s = sim_of<double>(h);
+  s->compute_macro();
+  copy_out(s->phi, phi); copy_out(s->mu, mu); copy_out(s->ux, ux); copy_out(s->uy, uy);
+  copy_out(s->pr, pr); copy_out(s->rho, rho); copy_out(s->S, S);
+}
+void orc_get_state(void* h, double* f, double* g, double* Sp) {
+  Sim<double>* s = sim_of<double>(h);
+  copy_out(s->f, f); copy_out(s->g, g); copy_out(s->Sp, Sp);
+}
+void orc_set_state(void* h, const double* f, const double* g, const double* Sp) {
+  Sim<double>* s = sim_of<double>(h);
+  const size_t n = s->cells();
+  for (size_t k = 0; k < Q * n; ++k) { s->f[k] = f[k]; s->g[k] = g[k]; }
+  for (size_t k = 0; k < n; ++k) s->Sp[k] = Sp[k];
+}
+
+// ------------------------------------------------ tangent-linear model (TLM)
+// dtheta = (d kappa, d beta, d alpha, d tau_f, d nu_A, d nu_B).
+void* orc_tlm_create(const orc_params* p, const double* dtheta) {
+  Sim<Dual>* s = new Sim<Dual>(*p);
+  if (dtheta) {
+    s->th.kappa.d = dtheta[0];
+    s->th.beta.d = dtheta[1];
+    s->th.alpha.d = dtheta[2];
+    s->th.tau_f.d = dtheta[3];
+    s->th.nu_A.d = dtheta[4];
+    s->th.nu_B.d = dtheta[5];
+  }
+  return s;
+}
+void orc_tlm_destroy(void* h) { delete sim_of<Dual>(h); }
+void orc_tlm_init(void* h, const double* phi0, const double* dphi0) {
+  Sim<Dual>* s = sim_of<Dual>(h);
+  const size_t n = s->cells();
+  std::vector<Dual> ph(n);
+  for (size_t k = 0; k < n; ++k) ph[k] = Dual(phi0[k], dphi0 ? dphi0[k] : 0.0);
+  s->init(ph.data(), nullptr, nullptr);
+}
+void orc_tlm_set_state(void* h, const double* f, const double* df, const double* g,
+                       const double* dg, const double* Sp, const double* dSp) {
+  Sim<Dual>* s = sim_of<Dual>(h);
+  const size_t n = s->cells();
+  for (size_t k = 0; k < Q * n; ++k) {
+    s->f[k] = Dual(f[k], df ? df[k] : 0.0);
+    s->g[k] = Dual(g[k], dg ? dg[k] : 0.0);
+  }
+  for (size_t k = 0; k < n; ++k) s->Sp[k] = Dual(Sp[k], dSp ? dSp[k] : 0.0);
+}
+void orc_tlm_step(void* h, int64_t n) {
+  for (int64_t k = 0; k < n; ++k) sim_of<Dual>(h)->step();
+}
+void orc_tlm_get_state(void* h, double* f, double* df, double* g, double* dg, double* Sp,
+                       double* dSp) {
+  Sim<Dual>* s = sim_of<Dual>(h);
+  for (size_t k = 0; k < s->f.size(); ++k) {
+    if (f) f[k] = s->f[k].v;
+    if (df) df[k] = s->f[k].d;
+    if (g) g[k] = s->g[k].v;
+    if (dg) dg[k] = s->g[k].d;
+  }
+  for (size_t k = 0; k < s->Sp.size(); ++k) {
+    if (Sp) Sp[k] = s->Sp[k].v;
+    if (dSp) dSp[k] = s->Sp[k].d;
+  }
+}
+// Tangent of the order parameter of the current state (phi = sum_i f_i).
+void orc_tlm_phi(void* h, double* phi, double* dphi) {
+  Sim<Dual>* s = sim_of<Dual>(h);
+  const size_t n = s->cells();
+  for (size_t k = 0; k < n; ++k) {
+    Dual a = 0.0;
+    for (int i = 0; i < Q; ++i) a += s->f[i * n + k];
+    if (phi) phi[k] = a.v;
+    if (dphi) dphi[k] = a.d;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,401 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these retypes an oracle formula: each checks the oracle against a
+moment identity the paper states, a closed form, a physical limit recovered
+by the Chapman-Enskog analysis, a symmetry, or an independent fixture
+(the Newton-solved discrete equilibrium of ``equilibrium.py``).
+"""
+import numpy as np
+import pytest
+
+import equilibrium
+import oracle
+from paper_2311_10827_amd import inputs
+
+CX, CY, W, CS2 = oracle.lattice()
+
+
+def test_lattice_isotropy():
+    # D2Q9 (Sec. 2.2, eq. eq:ci): weights sum to 1, odd moments vanish,
+    # second moment c_s^2 I with c_s^2 = 1/3, fourth moment isotropic.
+    assert CS2 == pytest.approx(1.0 / 3.0, abs=1e-16)
+    assert W.sum() == pytest.approx(1.0, abs=1e-15)
+    c = np.stack([CX, CY], 1).astype(float)
+    assert np.abs((W[:, None] * c).sum(0)).max() < 1e-16
+    M2 = np.einsum("i,ia,ib->ab", W, c, c)
+    assert np.abs(M2 - CS2 * np.eye(2)).max() < 1e-16
+    M4 = np.einsum("i,ia,ib,ic,id->abcd", W, c, c, c, c)
+    d = np.eye(2)
+    iso = CS2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+                      + np.einsum("ad,bc->abcd", d, d))
+    assert np.abs(M4 - iso).max() < 1e-16
+    M3 = np.einsum("i,ia,ib,ic->abc", W, c, c, c)
+    assert np.abs(M3).max() < 1e-16
+    # one rest velocity, four axis (|c|=1), four diagonal (|c|^2=2)
+    n2 = CX ** 2 + CY ** 2
+    assert sorted(n2.tolist()) == [0, 1, 1, 1, 1, 2, 2, 2, 2]
+
+
+@pytest.mark.parametrize("m,n", [(1, 0), (0, 2), (3, 1), (2, 5), (7, 3)])
+def test_stencil_fourier_symbols(m, n):
+    # Sec. 2.3.2, eqs. gradient and Laplace on a periodic grid: exact symbols.
+    nx, ny = 16, 12
+    prm = oracle.Params(nx=nx, ny=ny)
+    kx, ky = 2 * np.pi * m / nx, 2 * np.pi * n / ny
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    th = kx * X + ky * Y
+    gx, gy = oracle.gradient(prm, np.cos(th))
+    ex = -np.sin(kx) * (2.0 / 3 + np.cos(ky) / 3) * np.sin(th)
+    ey = -np.sin(ky) * (2.0 / 3 + np.cos(kx) / 3) * np.sin(th)
+    assert np.abs(gx - ex).max() < 1e-14 and np.abs(gy - ey).max() < 1e-14
+    lap = oracle.laplacian(prm, np.cos(th))
+    sym = 4.0 / 3 * (np.cos(kx) + np.cos(ky)) + 2.0 / 3 * np.cos(kx) * np.cos(ky) - 10.0 / 3
+    assert np.abs(lap - sym * np.cos(th)).max() < 1e-14
+
+
+def test_stencils_exact_on_polynomials_interior():
+    # Second-order stencils are exact on linear (gradient) and quadratic
+    # (Laplacian) fields away from walls.
+    nx, ny = 11, 9
+    prm = oracle.Params(nx=nx, ny=ny, bc_x=oracle.WALL, bc_y=oracle.WALL)
+    X, Y = np.meshgrid(np.arange(nx, dtype=float), np.arange(ny, dtype=float))
+    gx, gy = oracle.gradient(prm, 0.3 + 1.7 * X - 0.9 * Y)
+    sl = (slice(1, -1), slice(1, -1))
+    assert np.abs(gx[sl] - 1.7).max() < 1e-13 and np.abs(gy[sl] + 0.9).max() < 1e-13
+    for q, want in [(X * X, 2.0), (Y * Y, 2.0), (X * Y, 0.0), (X * X - Y * Y, 0.0)]:
+        assert np.abs(oracle.laplacian(prm, q)[sl] - want).max() < 1e-12
+
+
+def test_mirror_walls_give_neumann_laplacian():
+    # With mirrored ghosts the Laplacian of a field sums to zero over the box
+    # (discrete Neumann problem: no flux through the walls).
+    rng = np.random.default_rng(1)
+    prm = oracle.Params(nx=13, ny=7, bc_x=oracle.WALL, bc_y=oracle.WALL)
+    assert abs(oracle.laplacian(prm, rng.standard_normal((7, 13))).sum()) < 1e-12
+    prm = oracle.Params(nx=13, ny=7, bc_x=oracle.WALL)
+    assert abs(oracle.laplacian(prm, rng.standard_normal((7, 13))).sum()) < 1e-12
+
+
+def test_feq_and_source_moments():
+    # Sec. 2.3.1, eq. sumfeqandF: sum f^eq = phi, sum c f^eq = 0,
+    # sum c c f^eq = c_s^2 alpha mu I; sum F = -u.grad(phi), sum c F = 0, sum c c F = 0.
+    rng = np.random.default_rng(2)
+    c = np.stack([CX, CY], 1).astype(float)
+    for _ in range(20):
+        phi, mu, S, alpha = rng.uniform(-2, 2), rng.uniform(-1, 1), rng.uniform(-1, 1), rng.uniform(0.2, 3)
+        prm = oracle.Params(nx=1, ny=1, alpha=alpha)
+        fe = oracle.feq(prm, phi, mu)
+        assert fe.sum() == pytest.approx(phi, abs=1e-15)
+        assert np.abs(c.T @ fe).max() < 1e-15
+        assert np.abs(np.einsum("i,ia,ib->ab", fe, c, c) - CS2 * alpha * mu * np.eye(2)).max() < 1e-15
+        F = oracle.source(prm, S)
+        assert F.sum() == pytest.approx(-S, abs=1e-15)
+        assert np.abs(c.T @ F).max() < 1e-16
+        assert np.abs(np.einsum("i,ia,ib->ab", F, c, c)).max() < 1e-15
+
+
+def test_geq_and_forcing_moments():
+    # Moments that the NS-LBE needs for the Chapman-Enskog recovery of the
+    # incompressible NS equations with force F (derived from Sec. 2.3.2,
+    # eqs. G_i, Siu, GGi).
+    rng = np.random.default_rng(3)
+    c = np.stack([CX, CY], 1).astype(float)
+    prm = oracle.Params(nx=1, ny=1)
+    for _ in range(20):
+        p, rho = rng.uniform(-1, 1), rng.uniform(0.5, 1000)
+        u = rng.uniform(-0.1, 0.1, 2)
+        ge = oracle.geq(prm, p, rho, u[0], u[1])
+        assert abs(ge.sum()) < 1e-12 * rho
+        assert np.abs(c.T @ ge - rho * u).max() < 1e-12 * rho
+        P2 = np.einsum("i,ia,ib->ab", ge, c, c)
+        assert np.abs(P2 - (p * np.eye(2) + rho * np.outer(u, u))).max() < 1e-12 * rho
+        tau = rng.uniform(0.51, 2.0)
+        F, gr = rng.uniform(-1, 1, 2), rng.uniform(-1, 1, 2)
+        G = oracle.forcing(prm, tau, u[0], u[1], F[0], F[1], gr[0], gr[1])
+        k = 1 - 1 / (2 * tau)
+        assert G.sum() == pytest.approx(k * u @ gr, abs=1e-15)
+        assert np.abs(c.T @ G - k * F).max() < 1e-15
+        want = k / 3 * ((u @ gr) * np.eye(2) + np.outer(u, gr) + np.outer(gr, u))
+        assert np.abs(np.einsum("i,ia,ib->ab", G, c, c) - want).max() < 1e-15
+
+
+def test_macro_inverts_equilibrium():
+    # With F = 0 and grad(rho) = 0 the velocity and pressure recovered from
+    # g = g^eq(p, u) are p and u (Sec. 2.3.2, macroscopic subequations).
+    rng = np.random.default_rng(4)
+    prm = oracle.Params(nx=1, ny=1)
+    for _ in range(20):
+        p, rho = rng.uniform(-1, 1), rng.uniform(0.5, 1000)
+        u = rng.uniform(-0.1, 0.1, 2)
+        ux, uy, pp = oracle.macro(prm, oracle.geq(prm, p, rho, u[0], u[1]), rho, 0, 0, 0, 0)
+        assert ux == pytest.approx(u[0], abs=1e-15) and uy == pytest.approx(u[1], abs=1e-15)
+        assert pp == pytest.approx(p, abs=1e-12 * rho)
+
+
+@pytest.mark.parametrize("sigma,W,dphi", [(0.01, 4.0, 2.0), (1e-3, 5.0, 2.0), (0.005, 8.0, 1.0)])
+def test_kappa_beta_from_sigma_W(sigma, W, dphi):
+    # The flat tanh profile of width W (Sec. 3.1, eq. flatinitial) is a
+    # continuum equilibrium psi'(phi) = kappa phi'' exactly when beta obeys
+    # eq. beta, and its excess free energy kappa * int phi'^2 equals sigma
+    # of eq. suiface_tension.  Checked by quadrature and differences.
+    kappa, beta = oracle.kappa_beta(sigma, W, dphi)
+    pa, pb = dphi / 2, -dphi / 2
+    h = 1e-3
+    x = np.arange(-20 * W, 20 * W + h, h)
+    phi = 0.5 * dphi * np.tanh(2 * x / W)
+    d1 = np.gradient(phi, h)
+    d2 = np.gradient(d1, h)
+    dpsi = 4 * beta * (phi - pa) * (phi - pb) * phi
+    assert np.abs(dpsi - kappa * d2)[100:-100].max() < 1e-5 * beta * dphi ** 3
+    assert kappa * np.trapezoid(d1 * d1, x) == pytest.approx(sigma, rel=1e-6)
+
+
+def _wb_state(shape, bcx):
+    wl = inputs.FLAT
+    if shape == "flat":
+        prm = oracle.params_for(wl, nx=64, ny=4)
+        phi0 = inputs.flat_interface(64, 4, 4.0, 32.0)
+        wall = True
+    else:
+        prm = oracle.params_for(inputs.DROPLET, nx=48, ny=48, bc_x=bcx)
+        phi0 = inputs.droplet(48, 48, 12.0, 4.0, 23.6, 24.3)
+        wall = bcx == oracle.WALL
+    ps, mu0, hist = equilibrium.solve(phi0, prm.kappa, prm.beta, prm.phi_A, prm.phi_B,
+                                      wall_x=wall)
+    assert hist[-1] < 1e-15
+    return prm, ps, mu0
+
+
+@pytest.mark.parametrize("shape,bcx", [("flat", 1), ("drop", 0), ("drop", 1)])
+def test_well_balanced_fixed_point(shape, bcx):
+    # The paper's central claim (Sec. 2.3.1, after eq. mobility; Sec. 3):
+    # at the discrete phase equilibrium the velocity is zero to machine
+    # accuracy and phi does not move.  Independent fixture: Newton solve of
+    # mu_h(phi*) = const, sum(phi*) fixed.
+    prm, ps, mu0 = _wb_state(shape, bcx)
+    for n in (1, 10, 300):
+        s = oracle.Sim(prm).init(ps)
+        s.step(n)
+        m = s.moments()
+        umax = np.hypot(m["ux"], m["uy"]).max()
+        E = 0.5 * (m["rho"] * (m["ux"] ** 2 + m["uy"] ** 2)).sum()
+        assert umax <= 1e-14, (n, umax)
+        assert np.abs(m["phi"] - ps).max() <= 1e-12
+        assert E <= 1e-26
+        assert np.abs(m["mu"] - mu0).max() <= 1e-15
+
+
+def test_flat_interface_relaxes_to_discrete_equilibrium():
+    # Flat interface, 256 x 4, walls in x, 20000 steps: phi departs from
+    # the continuum tanh by the lattice's discrete equilibrium offset
+    # (1.536e-2 for W = 4, from the independent Newton fixture), approaches
+    # that discrete equilibrium, and the velocity stays small.
+    wl = inputs.FLAT
+    prm = oracle.params_for(wl)
+    phi0 = inputs.flat_interface()
+    ps, mu0, _ = equilibrium.solve(phi0, prm.kappa, prm.beta, 1.0, -1.0, wall_x=True)
+    assert np.abs(ps - phi0).max() == pytest.approx(1.5358e-2, abs=2e-6)
+    s = oracle.Sim(prm).init(phi0)
+    s.step(5000)
+    d5 = np.abs(s.moments()["phi"] - ps).max()
+    s.step(15000)
+    m = s.moments()
+    d20 = np.abs(m["phi"] - ps).max()
+    assert d20 < d5 < 5e-3
+    assert 1.4e-2 <= np.abs(m["phi"] - phi0).max() <= 1.7e-2
+    assert np.hypot(m["ux"], m["uy"]).max() < 1e-5
+    assert abs(m["uy"]).max() < 1e-18   # no motion along a flat interface
+
+
+@pytest.mark.parametrize("bcx", [0, 1])
+def test_phi_budget_identity(bcx):
+    # Collision conserves sum_i f_i except for the source (whose zeroth
+    # moment is -S, Sec. 2.3.1, eq. sumfeqandF), and streaming or bounce-back
+    # permutes values, so sum_x phi(t+1) - sum_x phi(t) = -sum_x (3/2 S - 1/2 S_prev).
+    wl = inputs.COALESCENCE
+    prm = oracle.params_for(wl, nx=40, ny=32, bc_x=bcx)
+    phi0 = inputs.two_drops(40, 32, 8.0, 5.0, noise=1e-3)
+    s = oracle.Sim(prm).init(phi0)
+    s.step(30)
+    for _ in range(10):
+        _, _, Sp = s.get_state()
+        m0 = s.moments()
+        s.step(1)
+        m1 = s.moments()
+        _, _, S = s.get_state()
+        lhs = m1["phi"].sum() - m0["phi"].sum()
+        rhs = -(1.5 * S - 0.5 * Sp).sum()
+        assert abs(lhs - rhs) <= 1e-13 * np.abs(m0["phi"]).sum()
+        assert abs(rhs) > 1e-12   # the test is not vacuous: there is motion
+
+
+def test_laplace_law():
+    # Young-Laplace in 2-D: Phat = p + phi mu - psi(phi) jumps by sigma/R
+    # across a drop at mechanical equilibrium (grad p = -phi grad mu, with
+    # mu from Sec. 2.1, eq. chemical_potencial); the jump builds in a few
+    # thousand steps while bulk mu stays near zero.
+    sig, W, L, R = 5e-3, 4.0, 64, 16
+    kappa, beta = oracle.kappa_beta(sig, W, 2.0)
+    prm = oracle.Params(nx=L, ny=L, rho_A=10.0, rho_B=1.0, kappa=kappa, beta=beta, M=0.2)
+    phi0 = inputs.droplet(L, L, R, W, L / 2, L / 2)
+    X, Y = np.meshgrid(np.arange(L) - L / 2, np.arange(L) - L / 2)
+    r = np.hypot(X, Y)
+    s = oracle.Sim(prm).init(phi0)
+    s.step(10000)
+    m = s.moments()
+    ph = m["phi"]
+    Ph = m["p"] + ph * m["mu"] - beta * (ph - 1) ** 2 * (ph + 1) ** 2
+    po, pi = ph[r > R + 12].mean(), ph[r < R / 2].mean()
+    Reff = np.sqrt(((ph - po) / (pi - po)).sum() / np.pi)
+    ratio = (Ph[r < R / 2].mean() - Ph[r > R + 12].mean()) / (sig / Reff)
+    assert 0.97 <= ratio <= 1.02, ratio
+
+
+@pytest.mark.parametrize("phase", [1.0, -1.0])
+def test_uniform_body_force_momentum(phase):
+    # Guo-type forcing: with g = 0 initially and a uniform body force G,
+    # momentum grows by G per step and rho u = (t + 1/2) G exactly
+    # (Sec. 2.3.2, eq. GGi and the rho u = sum c g + F/2 recovery).
+    prm = oracle.Params(nx=8, ny=6, rho_A=3.0, rho_B=1.5, gx=1e-5, gy=-2e-5)
+    s = oracle.Sim(prm).init(np.full((6, 8), phase))
+    s.step(37)
+    m = s.moments()
+    rho = 3.0 if phase > 0 else 1.5
+    assert np.abs(m["rho"] - rho).max() < 1e-15
+    assert np.abs(m["ux"] * rho - 37.5e-5).max() < 1e-17
+    assert np.abs(m["uy"] * rho + 37.5 * 2e-5).max() < 1e-17
+
+
+@pytest.mark.parametrize("phase", [1.0, -1.0])
+def test_shear_wave_decay(phase):
+    # nu = c_s^2 (tau_g - 1/2) (Sec. 2.3.2) with nu linear in phi: a
+    # transverse wave decays at nu k^2 in each pure phase (O(k^2) lattice error).
+    nx, ny = 64, 4
+    k = 2 * np.pi / nx
+    prm = oracle.Params(nx=nx, ny=ny, rho_A=3.0, rho_B=1.0, nu_A=0.05, nu_B=0.2)
+    X = np.broadcast_to(np.arange(nx, dtype=float), (ny, nx))
+    s = oracle.Sim(prm).init(np.full((ny, nx), phase), None, 1e-6 * np.sin(k * X))
+    amp = []
+    for _ in range(4):
+        s.step(100)
+        m = s.moments()
+        amp.append((m["uy"] * np.sin(k * X)).sum() / (np.sin(k * X) ** 2).sum())
+    rate = -np.log(amp[-1] / amp[0]) / 300
+    nu = 0.05 if phase > 0 else 0.2
+    assert rate == pytest.approx(nu * k * k, rel=5e-3)
+
+
+def test_sound_wave_speed():
+    # Sound speed of the pressure-based NS-LBE (derived from Sec. 2.3.2,
+    # eq. G_i and the pressure recovery): collision conserves
+    # P = sum_{i!=0} g_i = (1 - w_0) p / c_s^2 and the momentum, streaming gives
+    # dP/dt + div(rho u) = 0 and d(rho u)/dt = -grad p, so sound travels at
+    # c^2 = c_s^2 / (1 - w_0) = 3/5.  A longitudinal wave has period 2 pi/(c k).
+    nx, ny = 64, 4
+    k = 2 * np.pi / nx
+    prm = oracle.Params(nx=nx, ny=ny, nu_A=0.02, nu_B=0.02)
+    X = np.broadcast_to(np.arange(nx, dtype=float), (ny, nx))
+    s = oracle.Sim(prm).init(np.full((ny, nx), 1.0), 1e-6 * np.sin(k * X), None)
+    a = []
+    for _ in range(260):
+        m = s.moments()
+        a.append((m["ux"] * np.sin(k * X)).sum())
+        s.step(1)
+    a = np.array(a)
+    z = [i + a[i] / (a[i] - a[i + 1]) for i in range(len(a) - 1) if a[i] * a[i + 1] < 0]
+    period = 2 * np.mean(np.diff(z))
+    assert period == pytest.approx(2 * np.pi / (np.sqrt((1 / 3) / (1 - 4 / 9)) * k), rel=5e-3)
+
+
+def test_linear_cahn_hilliard_decay():
+    # Recovered CH equation (Sec. 2.3.1, eq. CH_equation3) with
+    # M = c_s^2 alpha (tau_f - 1/2) (eq. mobility): a small perturbation of the
+    # bulk phase A decays at M k^2 (psi''(phi_A) + kappa k^2), psi'' = 8 beta
+    # for phi_A = 1, phi_B = -1.
+    nx, ny = 64, 4
+    k = 2 * np.pi / nx
+    kappa, beta, M = 0.04, 0.005, 0.1
+    prm = oracle.Params(nx=nx, ny=ny, kappa=kappa, beta=beta, M=M, alpha=0.7)
+    X = np.broadcast_to(np.arange(nx, dtype=float), (ny, nx))
+    s = oracle.Sim(prm).init(1.0 + 1e-6 * np.sin(k * X))
+    amp = []
+    for _ in range(4):
+        s.step(250)
+        m = s.moments()
+        amp.append(((m["phi"] - 1) * np.sin(k * X)).sum() / (np.sin(k * X) ** 2).sum())
+    rate = -np.log(amp[-1] / amp[0]) / 750
+    assert rate == pytest.approx(M * k * k * (8 * beta + kappa * k * k), rel=5e-3)
+
+
+@pytest.mark.parametrize("u0", [0.02, -0.03])
+def test_advection_by_source_term(u0):
+    # With mu = 0 (kappa = beta = 0) and uniform density the CH-LBE reduces to
+    # d phi/dt + u.grad(phi) = 0, carried by the source of eq. F_i; a
+    # uniform flow translates phi by u0 t.
+    nx, ny, T = 64, 4, 400
+    k = 2 * np.pi / nx
+    prm = oracle.Params(nx=nx, ny=ny, kappa=0.0, beta=0.0, M=0.1)
+    X = np.broadcast_to(np.arange(nx, dtype=float), (ny, nx))
+    s = oracle.Sim(prm).init(0.1 * np.sin(k * X), np.full((ny, nx), u0), None)
+    s.step(T)
+    m = s.moments()
+    ph = m["phi"][0]
+    c, sn = (ph * np.cos(k * X[0])).sum(), (ph * np.sin(k * X[0])).sum()
+    shift = -np.arctan2(c, sn) / k
+    assert shift == pytest.approx(u0 * T, rel=5e-3)
+    assert np.hypot(c, sn) / (0.1 * nx / 2) == pytest.approx(1.0, abs=1e-4)
+    assert np.abs(m["ux"] - u0).max() < 1e-15
+
+
+def test_translation_invariance_periodic():
+    # Integer shifts commute with the periodic step, bit for bit.
+    prm = oracle.params_for(inputs.COALESCENCE, nx=32, ny=24)
+    phi0 = inputs.two_drops(32, 24, 6.0, 5.0, noise=1e-2)
+    a = oracle.Sim(prm).init(phi0).step(15).moments()
+    b = oracle.Sim(prm).init(np.roll(phi0, (5, 3), (0, 1))).step(15).moments()
+    for k in a:
+        assert np.array_equal(np.roll(a[k], (5, 3), (0, 1)), b[k]), k
+
+
+def test_mirror_symmetry_with_walls():
+    # A field mirror-symmetric about the channel centre stays symmetric.
+    prm = oracle.params_for(inputs.COALESCENCE, nx=30, ny=16, bc_x=oracle.WALL)
+    phi0 = inputs.two_drops(30, 16, 5.0, 5.0)
+    phi0 = 0.5 * (phi0 + phi0[:, ::-1])
+    m = oracle.Sim(prm).init(phi0).step(40).moments()
+    assert np.abs(m["phi"] - m["phi"][:, ::-1]).max() < 1e-14
+    assert np.abs(m["ux"] + m["ux"][:, ::-1]).max() < 1e-16
+    assert np.abs(m["ux"]).max() > 1e-9
+
+
+def test_tlm_matches_central_differences():
+    # The dual-number instantiation is the exact tangent of the FP64 step;
+    # check it against central differences of the plain oracle.
+    rng = np.random.default_rng(5)
+    prm = oracle.params_for(inputs.ADJOINT, nx=16, ny=12, bc_x=oracle.WALL)
+    phi0 = inputs.two_drops(16, 12, 3.0, 4.0, noise=1e-2)
+    s = oracle.Sim(prm).init(phi0).step(3)
+    f, g, Sp = s.get_state()
+    df, dg, dSp = (rng.standard_normal(a.shape) for a in (f, g, Sp))
+    dg *= 1e-3
+    dth = rng.standard_normal(6) * np.array([1e-3, 1e-4, 0.1, 0.05, 0.01, 0.01])
+    t = oracle.TLM(prm, dth).set_state(f, df, g, dg, Sp, dSp).step(4)
+    _, Jf, _, Jg, _, JS = t.get_state()
+    h = 1e-6
+
+    def run(sign):
+        q = oracle.Params(**{**prm.__dict__})
+        q.kappa += sign * h * dth[0]
+        q.beta += sign * h * dth[1]
+        alpha = q.alpha + sign * h * dth[2]
+        tau_f = prm.tau_f + sign * h * dth[3]
+        q.alpha = alpha
+        q.M = (tau_f - 0.5) * alpha / 3.0
+        q.nu_A += sign * h * dth[4]
+        q.nu_B += sign * h * dth[5]
+        o = oracle.Sim(q).set_state(f + sign * h * df, g + sign * h * dg, Sp + sign * h * dSp)
+        return o.step(4).get_state()
+
+    (fp, gp, Sp_p), (fm, gm, Sm) = run(1), run(-1)
+    for fd, tl in [((fp - fm) / (2 * h), Jf), ((gp - gm) / (2 * h), Jg), ((Sp_p - Sm) / (2 * h), JS)]:
+        assert np.abs(fd - tl).max() <= 1e-6 * np.abs(tl).max()
