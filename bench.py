@@ -1,0 +1,233 @@
+#!/usr/bin/env python
+"""Throughput of the well-balanced phase-field LBM step on one MI355X.
+
+Workload: 16384 x 16384 periodic grid, 2000 seeded non-overlapping drops with
+radius ~ U(20, 80), density ratio 100, nu 0.1/0.1, sigma 5e-4, M 0.05, W 4
+(synthetic input; there is no dataset).  One step = the phi/mu stencil pass
+plus the fused collide-and-pull-stream pass, through the C ABI.
+
+Prints one JSON line: FP32 (deviation storage) MLUPS as the value, the FP64
+step beside it, the roofline of the collide-stream kernel measured with HIP
+events on the library's stream, and the CPU oracle timed on a bounded crop
+of the same field.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS & % HBM roofline, FP32 vs FP64 step; adjoint/forward step cost ratio"
+HBM_PEAK_GBPS = 8000.0
+# Algorithmic HBM bytes per lattice update of each kernel (per cell):
+#   collide-stream: 18 populations read + 18 written, phi and mu read once,
+#                   previous source read and new source written;
+#   phi/mu pass:    9 populations read, phi and mu written.
+COLLIDE_BYTES = {32: (18 + 18 + 2 + 2) * 4, 64: (18 + 18 + 2 + 2) * 8}
+PHIMU_BYTES = {32: (9 + 2) * 4, 64: (9 + 2) * 8}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_many_drops_16384.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def kernel_source_hash() -> str:
+    with open(os.path.join(ROOT, "paper_2311_10827_amd", "csrc", "lbmwb.hip"), "rb") as fh:
+        return hashlib.sha256(fh.read()).hexdigest()[:16]
+
+
+def measured_traffic(prec: int):
+    """HBM bytes per launch of the collide kernel from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    try:
+        with open(TRAFFIC_FILE) as fh:
+            t = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    rec = t.get(str(prec))
+    if not rec or t.get("source_sha256_16") != kernel_source_hash():
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl):
+    import torch
+    from paper_2311_10827_amd.sim import Sim, make_params
+
+    p = make_params(wl, precision=prec)
+    sim = Sim(p, phi0_dev, device=phi0_dev.device)
+    stream = sim.stream
+    ncell = wl.nx * wl.ny
+    log(f"[bench] fp{prec}: warmup {warmup}")
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    log(f"[bench] fp{prec}: timing {steps} steps")
+    t0 = time.perf_counter()
+    e0.record(stream)
+    sim.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1)
+    # per-kernel durations with HIP events recorded by the library on its stream
+    log(f"[bench] fp{prec}: per-kernel timing over {kernel_steps} steps")
+    sim.timing(True)
+    sim.step(kernel_steps)
+    k1, k2, n = sim.kernel_times()
+    sim.timing(False)
+    m = sim.moments()
+    d = m["diag"]
+    del m
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    avg_k1, avg_k2 = k1 / n, k2 / n
+    ach = COLLIDE_BYTES[prec] * ncell / (avg_k2 * 1e-3) / 1e9
+    traffic = measured_traffic(prec)
+    return {
+        "mlups": ncell * steps / (ms * 1e-3) / 1e6,
+        "ms_per_step": ms / steps,
+        "wall_s": wall,
+        "kernels_ms": {"phi_mu": avg_k1, "collide_stream": avg_k2},
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+        },
+        "phi_mu_GBps": round(PHIMU_BYTES[prec] * ncell / (avg_k1 * 1e-3) / 1e9, 1),
+        "step_GBps_alg": round((COLLIDE_BYTES[prec] + PHIMU_BYTES[prec]) * ncell / (ms / steps * 1e-3) / 1e9, 1),
+        "diag_after": {k: d[k] for k in ("sum_phi", "max_u", "min_rho", "n_nonfinite", "step")},
+    }
+
+
+def stream_copy_probe(device, nbytes=4 << 30, reps=10):
+    import torch
+    from paper_2311_10827_amd.sim import stream_copy
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device=device).fill_(1.0)
+    b = torch.empty_like(a)
+    stream_copy(b, a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        stream_copy(b, a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
+def cpu_baseline(wl, seconds: float):
+    """FP64 oracle (plain loops, OpenMP over rows) on a 1024^2 crop of the field."""
+    import numpy as np
+    import oracle
+    from paper_2311_10827_amd import inputs
+    oracle.build(force=False)
+    n = 1024
+    phi = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W,
+                            window=(0, 0, n, n))
+    o = oracle.Sim(oracle.params_for(wl, nx=n, ny=n)).init(phi)
+    t = time.perf_counter()
+    o.step(2)
+    per = (time.perf_counter() - t) / 2
+    k = max(2, int(seconds / max(per, 1e-6)))
+    t = time.perf_counter()
+    o.step(k)
+    dt = time.perf_counter() - t
+    return {
+        "value": round(n * n * k / dt / 1e6, 3),
+        "unit": "MLUPS",
+        "cores": oracle.get_threads(),
+        "kind": "oracle",
+        "sample": f"1024x1024 crop of the 16384^2 many-drop field (periodic), {k} FP64 steps, {dt:.1f} s",
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--fp64-steps", type=int, default=None, help="default: --steps")
+    ap.add_argument("--kernel-steps", type=int, default=100)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
+              "slab decomposition is a design, not a build, here", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2311_10827_amd import inputs
+
+    wl = inputs.THROUGHPUT
+    dev = torch.device("cuda:0")
+    log("[bench] generating the 16384^2 many-drop field")
+    phi0 = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
+    phi0_dev = torch.from_numpy(phi0).to(dev)
+    del phi0
+    r32 = run_gpu(phi0_dev, 32, args.steps, args.warmup, args.kernel_steps, wl)
+    r64 = None
+    if not args.no_fp64:
+        r64 = run_gpu(phi0_dev, 64, args.fp64_steps or args.steps, args.warmup, args.kernel_steps, wl)
+    del phi0_dev
+    torch.cuda.empty_cache()
+    copy_gbps = None if args.no_copy else stream_copy_probe(dev)
+    cpu = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC,
+        "value": round(r32["mlups"], 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(r32["ms_per_step"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "many_drops_16384: 16384x16384 periodic, 2000 drops R~U(20,80), "
+                        "density ratio 100, nu 0.1/0.1, sigma 5e-4, M 0.05, W 4",
+            "nx": wl.nx, "ny": wl.ny, "precision": "fp32 deviation storage",
+            "parallelism": "single GPU",
+        },
+        "roofline": r32["roofline"],
+        "cpu_baseline": cpu,
+        "kernels_ms": r32["kernels_ms"],
+        "phi_mu_GBps": r32["phi_mu_GBps"],
+        "step_GBps_alg": r32["step_GBps_alg"],
+        "stream_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
+        "fp64": None if r64 is None else {
+            "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 4),
+            "roofline": r64["roofline"], "kernels_ms": r64["kernels_ms"],
+            "phi_mu_GBps": r64["phi_mu_GBps"], "step_GBps_alg": r64["step_GBps_alg"],
+        },
+        "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),
+        "adjoint_forward_ratio": None,
+        "diag_after": r32["diag_after"],
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

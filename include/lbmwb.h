@@ -1,0 +1,220 @@
+/*
+ * lbmwb.h -- C ABI of the MI355X (gfx950) library for the well-balanced
+ * phase-field lattice Boltzmann step of Ju, Liu, Yan, Bao, Sun and Guo,
+ * "A well-balanced lattice Boltzmann model for binary fluids based on the
+ * incompressible phase-field theory" (arXiv 2311.10827).
+ *
+ * One time step updates two D2Q9 populations on a 2-D grid:
+ *   - the order-parameter population, the paper's f_i (Sec. 2.3.1, eq. BGK),
+ *     whose equilibrium carries no velocity; convection u.grad(phi) enters as
+ *     a source term F_i plus half its time derivative (eqs. H_i, F_i);
+ *   - the pressure/velocity population, the paper's g_i (Sec. 2.3.2,
+ *     eq. BGK-NS), driven by the potential-form force F = -phi grad(mu) + G.
+ * Names in this header follow the paper: "f" is always the order-parameter
+ * population and "g" the hydrodynamic one.
+ *
+ * Conventions
+ *   - Lattice units, delta_x = delta_t = 1, c_s^2 = 1/3.
+ *   - Velocity order: 0 rest; 1 (+1,0); 2 (0,+1); 3 (-1,0); 4 (0,-1);
+ *     5 (+1,+1); 6 (-1,+1); 7 (-1,-1); 8 (+1,-1).
+ *   - Fields are row-major [ny][nx], x fastest; cell (i, j) is at x = i, y = j.
+ *   - Phase A is the paper's "l" phase (phi_A), phase B its "v" phase.
+ *
+ * Memory and streams
+ *   - The library never allocates or frees device memory.  The caller
+ *     allocates the state (lbm_state_bytes) and workspace
+ *     (lbm_workspace_bytes) buffers on the device, keeps them alive for the
+ *     context's lifetime and owns them; the context only borrows them.
+ *   - Every call is ordered on the HIP stream given to lbm_init and does not
+ *     block the host, except where a function says it synchronises.
+ *   - A context is not thread-safe.  Pointer arguments marked "device" must
+ *     be device memory of the GPU current at lbm_init.
+ *
+ * Errors: every int-returning function returns LBM_OK (0) or a negative code;
+ * lbm_strerror() names it and lbm_last_error() gives the context's detail
+ * text.  No C++ exception crosses this interface.
+ */
+#ifndef LBMWB_H
+#define LBMWB_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define LBM_OK 0
+#define LBM_EINVAL (-1)     /* bad argument: size, relaxation time <= 1/2, rho <= 0, ... */
+#define LBM_EHIP (-2)       /* a HIP runtime call or kernel launch failed */
+#define LBM_ENONFINITE (-3) /* diagnostics saw NaN/Inf or a non-positive density */
+#define LBM_ESTATE (-4)     /* call made in the wrong state */
+
+enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
+
+/*
+ * Problem parameters, in the paper's notation.
+ *   phi_A, phi_B   order parameter of the two bulk phases (Sec. 2.1, eq. bulk_energy).
+ *   rho_A, rho_B   densities; rho is linear in phi between them (Sec. 2.3.2,
+ *                  sentence before eq. vis).
+ *   nu_A, nu_B     kinematic viscosities; nu is linear in phi (eq. vis) and
+ *                  tau_g = 1/2 + nu / c_s^2 per cell (Sec. 2.3.2).
+ *   kappa, beta    gradient and double-well coefficients (eqs. energy_function,
+ *                  bulk_energy).  With use_sigma_W = 1 they are derived from the
+ *                  surface tension sigma and interface width W instead
+ *                  (eqs. beta, suiface_tension).
+ *   M, alpha       mobility and the equilibrium's free parameter;
+ *                  tau_f = 1/2 + M / (c_s^2 alpha) (Sec. 2.3.1, eq. mobility).
+ *   gx, gy         body force G added to the interfacial force (Sec. 2.3.2).
+ *   bc_x, bc_y     LBM_PERIODIC, or LBM_WALL: half-way bounce-back for both
+ *                  populations, and phi, mu mirrored across the wall in the
+ *                  finite-difference stencils (the paper's tests are periodic).
+ *   precision      64: populations stored and updated in FP64.
+ *                  32: populations stored and updated in FP32, the rest
+ *                      population of f held as a deviation from
+ *                      (phi_A + phi_B) / 2; diagnostics stay FP64.
+ *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
+ *                  diagnostic pass every k steps (see lbm_step).
+ */
+typedef struct lbm_params {
+  int32_t nx, ny;
+  int32_t bc_x, bc_y;
+  int32_t precision;
+  int32_t use_sigma_W;
+  double phi_A, phi_B;
+  double rho_A, rho_B;
+  double nu_A, nu_B;
+  double kappa, beta;
+  double sigma, W;
+  double M, alpha;
+  double gx, gy;
+  int32_t diag_every;
+  int32_t reserved;
+} lbm_params;
+
+/* Derived constants (lattice units). */
+typedef struct lbm_derived {
+  double kappa, beta;     /* as used by the step */
+  double sigma, W;        /* surface tension and width implied by kappa, beta */
+  double tau_f;           /* 1/2 + M / (c_s^2 alpha) */
+  double tau_gA, tau_gB;  /* 1/2 + nu_A / c_s^2, 1/2 + nu_B / c_s^2 */
+  double alpha;
+} lbm_derived;
+
+/*
+ * FP64 diagnostics of the pre-collision state at time `step`.
+ * source_sum = sum_x (3/2 S(n) - 1/2 S(n-1)) with S = u.grad(phi); the next
+ * step changes sum_x phi by exactly -source_sum (the zeroth moment of the
+ * source, Sec. 2.3.1, eq. sumfeqandF).  Sums and extrema are reduced in a
+ * fixed order, so they are bitwise reproducible.
+ */
+typedef struct lbm_diag {
+  double sum_phi;
+  double source_sum;
+  double kinetic_energy;  /* 1/2 sum_x rho |u|^2 (Sec. 3.1) */
+  double max_u;           /* max_x |u| */
+  double min_rho, max_rho;
+  double mu_min, mu_max;
+  double phi_min, phi_max;
+  int64_t n_nonfinite;    /* cells whose phi, mu, u or p is not finite */
+  int64_t step;
+} lbm_diag;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Validate `p` and fill `out`.  LBM_EINVAL on: nx, ny < 1; a plane of more
+ * than 2^31 - 1 cells; bc not 0/1; precision not 32/64; phi_A == phi_B;
+ * rho_A, rho_B <= 0; nu_A, nu_B <= 0; M <= 0; alpha <= 0; kappa or beta
+ * < 0 (or sigma, W <= 0 with use_sigma_W); diag_every < 0. */
+int lbm_derive(const lbm_params* p, lbm_derived* out);
+
+/* Bytes the caller must allocate for the state and the workspace (0 if `p`
+ * is invalid).  The state holds two population buffers and the phi, mu and
+ * source planes; its layout is private to the library (256-byte aligned
+ * planes).  The workspace holds reduction partials. */
+size_t lbm_state_bytes(const lbm_params* p);
+size_t lbm_workspace_bytes(const lbm_params* p);
+
+/*
+ * Create a context and write the initial state (time 0):
+ *   f = f^eq(phi0, mu(phi0)) (Sec. 2.3.1, eq. H_i),
+ *   g = g^eq(p = 0, u0) (Sec. 2.3.2, eq. G_i),
+ *   previous-step source = S(0) computed from that state.
+ * phi0: device, FP64 [ny][nx], required.  ux0, uy0: device, FP64 [ny][nx], or
+ * NULL for zero.  state, workspace: device buffers of at least the sizes
+ * above, 256-byte aligned.  stream: a hipStream_t, or NULL for the null
+ * stream.  On success *out owns host-side resources until lbm_destroy.
+ */
+int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace,
+             const double* phi0, const double* ux0, const double* uy0, void* stream);
+
+/*
+ * Advance n >= 0 time steps.  One step is two kernels: the phi/mu stencil
+ * pass (phi = sum_i f_i, Sec. 2.3.1, eq. order-parameter; mu by eq.
+ * chemical_potencial with the isotropic Laplacian of Sec. 2.3.2, eq. Laplace)
+ * and the fused collide-and-pull-stream pass (Sec. 2.3.1, eq. BGK;
+ * Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi and the u, p recovery).
+ * Asynchronous.  With diag_every = k > 0 every k-th step also reduces the
+ * diagnostics of its pre-collision state; a pass that found a non-finite
+ * value or rho <= 0 makes a later lbm_step (or lbm_last_diag) return
+ * LBM_ENONFINITE once that pass has completed on the device.
+ */
+int lbm_step(lbm_ctx* ctx, int64_t n);
+
+/* Number of steps taken since lbm_init (or the step given to lbm_set_state). */
+int64_t lbm_step_count(const lbm_ctx* ctx);
+
+/*
+ * Moments of the current pre-collision state: phi, mu, ux, uy, p, rho.
+ * Each output is device FP64 [ny][nx] or NULL.  If diag is not NULL it
+ * receives the diagnostics (host struct); that makes the call synchronise
+ * the stream.  Does not advance time.
+ */
+int lbm_moments(lbm_ctx* ctx, double* phi, double* mu, double* ux, double* uy, double* p,
+                double* rho, lbm_diag* diag);
+
+/* Diagnostics of the latest fused diagnostic pass of lbm_step (host
+ * struct).  Synchronises the stream.  LBM_ESTATE if no pass ran yet;
+ * LBM_ENONFINITE if that pass saw a non-finite value or rho <= 0 (the struct
+ * is still filled). */
+int lbm_last_diag(lbm_ctx* ctx, lbm_diag* diag);
+
+/*
+ * Copy the pre-collision populations and the previous-step source of the
+ * periodic window [x0, x0 + w) x [y0, y0 + h) (coordinates taken modulo
+ * nx, ny) into device FP64 arrays f [9][h][w], g [9][h][w], Sp [h][w]; any
+ * may be NULL.  Requires 1 <= w <= nx, 1 <= h <= ny.
+ */
+int lbm_get_state(lbm_ctx* ctx, int32_t x0, int32_t y0, int32_t w, int32_t h, double* f,
+                  double* g, double* Sp);
+
+/* Replace the whole state by pre-collision populations f, g [9][ny][nx]
+ * and previous-step source Sp [ny][nx] (device FP64), and set the step
+ * counter to `step`. */
+int lbm_set_state(lbm_ctx* ctx, const double* f, const double* g, const double* Sp,
+                  int64_t step);
+
+/* Per-kernel timing with HIP events recorded on the context's stream.
+ * lbm_timing(ctx, 1) starts recording (clearing earlier records), 0 stops.
+ * lbm_kernel_times synchronises and returns the summed milliseconds of the
+ * phi/mu pass and of the collide-stream pass and the number of steps timed. */
+int lbm_timing(lbm_ctx* ctx, int enable);
+int lbm_kernel_times(lbm_ctx* ctx, double* ms_phi_mu, double* ms_collide, int64_t* steps);
+
+/* Bandwidth probe: copy `bytes` (a multiple of 16) from src to dst on
+ * `stream` with a plain streaming kernel (device pointers, 16-byte aligned,
+ * non-overlapping). */
+int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* Release the context's host resources (not the caller's buffers). */
+int lbm_destroy(lbm_ctx* ctx);
+
+const char* lbm_strerror(int code);
+/* Detail text of the context's most recent failure ("" if none). */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBMWB_H */

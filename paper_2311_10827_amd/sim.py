@@ -1,0 +1,164 @@
+"""PyTorch-side wrapper of the C ABI: device memory and streams only.
+
+PyTorch allocates the state and workspace buffers and provides the HIP
+stream; every step of the method runs in ``liblbmwb.so``.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional
+
+import torch
+
+from . import _lib
+from ._lib import LbmDiag, LbmParams, LbmDerived, check
+
+
+def make_params(workload=None, precision: int = 64, diag_every: int = 0, **over) -> LbmParams:
+    """C parameter block from a workload preset (``inputs.Workload``) and overrides.
+
+    A workload gives sigma and W; the library derives kappa and beta from them
+    (use_sigma_W = 1) unless ``kappa`` and ``beta`` are passed explicitly.
+    """
+    kw = dict(nx=0, ny=0, bc_x=0, bc_y=0, precision=precision, use_sigma_W=0, phi_A=1.0,
+              phi_B=-1.0, rho_A=1.0, rho_B=1.0, nu_A=0.1, nu_B=0.1, kappa=0.0, beta=0.0,
+              sigma=0.0, W=0.0, M=0.1, alpha=1.0, gx=0.0, gy=0.0, diag_every=diag_every,
+              reserved=0)
+    if workload is not None:
+        for k in ("nx", "ny", "bc_x", "bc_y", "phi_A", "phi_B", "rho_A", "rho_B", "nu_A", "nu_B",
+                  "sigma", "W", "M", "alpha"):
+            kw[k] = getattr(workload, k)
+        kw["use_sigma_W"] = 1
+    if "kappa" in over or "beta" in over:
+        kw["use_sigma_W"] = 0
+    kw.update(over)
+    return LbmParams(**kw)
+
+
+def derive(p: LbmParams) -> dict:
+    d = LbmDerived()
+    check(_lib.load().lbm_derive(ctypes.byref(p), ctypes.byref(d)), "lbm_derive")
+    return {k: getattr(d, k) for k, _ in d._fields_}
+
+
+def _dev_f64(a, shape, device) -> Optional[torch.Tensor]:
+    if a is None:
+        return None
+    t = torch.as_tensor(a, dtype=torch.float64, device=device).contiguous()
+    if tuple(t.shape) != tuple(shape):
+        raise ValueError(f"expected shape {tuple(shape)}, got {tuple(t.shape)}")
+    return t
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Sim:
+    """One simulation context on one GPU."""
+
+    def __init__(self, params: LbmParams, phi0, ux0=None, uy0=None, device="cuda:0"):
+        self.L = _lib.load()
+        self.p = params
+        self.derived = derive(params)
+        self.device = torch.device(device)
+        self.shape = (params.ny, params.nx)
+        nb = self.L.lbm_state_bytes(ctypes.byref(params))
+        nw = self.L.lbm_workspace_bytes(ctypes.byref(params))
+        if nb == 0 or nw == 0:
+            raise _lib.LbmError(_lib.LBM_EINVAL, "lbm_state_bytes")
+        with torch.cuda.device(self.device):
+            self.state = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            self.workspace = torch.empty(nw, dtype=torch.uint8, device=self.device)
+            self.stream = torch.cuda.current_stream(self.device)
+            phi0 = _dev_f64(phi0, self.shape, self.device)
+            ux0 = _dev_f64(ux0, self.shape, self.device)
+            uy0 = _dev_f64(uy0, self.shape, self.device)
+            ctx = ctypes.c_void_p()
+            rc = self.L.lbm_init(ctypes.byref(ctx), ctypes.byref(params),
+                                 ctypes.c_void_p(self.state.data_ptr()),
+                                 ctypes.c_void_p(self.workspace.data_ptr()), _ptr(phi0), _ptr(ux0),
+                                 _ptr(uy0), ctypes.c_void_p(self.stream.cuda_stream))
+            check(rc, "lbm_init")
+            self.ctx = ctx
+            self._keep = (phi0, ux0, uy0)
+            self.stream.synchronize()
+            self._keep = None
+
+    # -- lifecycle ---------------------------------------------------------
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.L.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- time stepping -------------------------------------------------------
+    def step(self, n: int = 1) -> "Sim":
+        check(self.L.lbm_step(self.ctx, int(n)), "lbm_step", self.ctx)
+        return self
+
+    @property
+    def step_count(self) -> int:
+        return int(self.L.lbm_step_count(self.ctx))
+
+    def moments(self, diag: bool = True):
+        out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device)
+               for k in ("phi", "mu", "ux", "uy", "p", "rho")}
+        d = LbmDiag()
+        rc = self.L.lbm_moments(self.ctx, *(_ptr(out[k]) for k in ("phi", "mu", "ux", "uy", "p", "rho")),
+                                ctypes.byref(d) if diag else None)
+        check(rc, "lbm_moments", self.ctx)
+        if diag:
+            out["diag"] = d.as_dict()
+        return out
+
+    def last_diag(self) -> dict:
+        d = LbmDiag()
+        rc = self.L.lbm_last_diag(self.ctx, ctypes.byref(d))
+        if rc not in (_lib.LBM_OK, _lib.LBM_ENONFINITE):
+            check(rc, "lbm_last_diag", self.ctx)
+        r = d.as_dict()
+        r["ok"] = rc == _lib.LBM_OK
+        return r
+
+    # -- state ---------------------------------------------------------------
+    def get_state(self, window=None):
+        """(f, g, Sp) pre-collision populations [9,h,w] and previous source [h,w]."""
+        x0, y0, w, h = window if window is not None else (0, 0, self.p.nx, self.p.ny)
+        f = torch.empty((9, h, w), dtype=torch.float64, device=self.device)
+        g = torch.empty((9, h, w), dtype=torch.float64, device=self.device)
+        Sp = torch.empty((h, w), dtype=torch.float64, device=self.device)
+        check(self.L.lbm_get_state(self.ctx, x0, y0, w, h, _ptr(f), _ptr(g), _ptr(Sp)),
+              "lbm_get_state", self.ctx)
+        return f, g, Sp
+
+    def set_state(self, f, g, Sp, step: int = 0) -> "Sim":
+        sh9 = (9,) + self.shape
+        f, g, Sp = _dev_f64(f, sh9, self.device), _dev_f64(g, sh9, self.device), _dev_f64(Sp, self.shape, self.device)
+        check(self.L.lbm_set_state(self.ctx, _ptr(f), _ptr(g), _ptr(Sp), int(step)), "lbm_set_state", self.ctx)
+        self.stream.synchronize()
+        return self
+
+    # -- timing ----------------------------------------------------------------
+    def timing(self, enable: bool) -> None:
+        check(self.L.lbm_timing(self.ctx, int(bool(enable))), "lbm_timing", self.ctx)
+
+    def kernel_times(self):
+        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        check(self.L.lbm_kernel_times(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+              "lbm_kernel_times", self.ctx)
+        return a.value, b.value, n.value
+
+
+def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
+    """Plain streaming copy kernel of the library (bandwidth probe)."""
+    L = _lib.load()
+    nbytes = src.numel() * src.element_size()
+    rc = L.lbm_stream_copy(ctypes.c_void_p(dst.data_ptr()), ctypes.c_void_p(src.data_ptr()), nbytes,
+                           ctypes.c_void_p(torch.cuda.current_stream(src.device).cuda_stream))
+    check(rc, "lbm_stream_copy")

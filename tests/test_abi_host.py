@@ -1,0 +1,99 @@
+"""Host-side checks of the C ABI: the library loads, exports every symbol the
+header declares, and validates parameters (no GPU compute calls)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2311_10827_amd import _lib, inputs
+from paper_2311_10827_amd.sim import make_params
+
+HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "lbmwb.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(lbm_[a-z_]+)\s*\(", txt)))
+
+
+def test_header_and_binding_agree():
+    assert declared_functions() == sorted(_lib.SYMBOLS)
+
+
+def test_library_exports_every_symbol():
+    L = _lib.load()
+    for name in declared_functions():
+        assert hasattr(L, name), name
+
+
+def _derive(p):
+    d = _lib.LbmDerived()
+    return _lib.load().lbm_derive(ctypes.byref(p), ctypes.byref(d)), d
+
+
+def test_derive_from_sigma_W():
+    rc, d = _derive(make_params(inputs.FLAT))
+    assert rc == 0
+    # Sec. 2.1, eqs. beta and suiface_tension, with sigma = 0.01, W = 4, dphi = 2
+    assert d.kappa == pytest.approx(0.015, rel=1e-15)
+    assert d.beta == pytest.approx(1.875e-3, rel=1e-15)
+    assert d.sigma == pytest.approx(0.01, rel=1e-14)
+    assert d.W == pytest.approx(4.0, rel=1e-14)
+    # Sec. 2.3.1 eq. mobility and Sec. 2.3.2: tau = 1/2 + 3 M / alpha, 1/2 + 3 nu
+    assert d.tau_f == pytest.approx(0.8, rel=1e-15)
+    assert d.tau_gA == pytest.approx(0.8, rel=1e-15) and d.tau_gB == pytest.approx(0.8, rel=1e-15)
+    rc, d = _derive(make_params(inputs.DROPLET))
+    assert rc == 0 and d.tau_gA == pytest.approx(0.53) and d.tau_gB == pytest.approx(0.8)
+    assert d.tau_f == pytest.approx(0.65)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(nx=0), dict(ny=-3), dict(bc_x=2), dict(precision=16), dict(phi_A=-1.0),
+    dict(rho_B=0.0), dict(rho_A=-2.0), dict(nu_A=0.0), dict(M=0.0), dict(alpha=0.0),
+    dict(kappa=-1.0, beta=0.0), dict(diag_every=-1), dict(nx=65536, ny=65536),
+    dict(gx=float("nan")),
+])
+def test_derive_rejects(bad):
+    p = make_params(inputs.FLAT, **bad)
+    rc, _ = _derive(p)
+    assert rc == _lib.LBM_EINVAL
+    assert _lib.load().lbm_state_bytes(ctypes.byref(p)) == 0
+
+
+def test_sigma_W_must_be_positive():
+    p = make_params(inputs.FLAT)
+    p.sigma = 0.0
+    assert _derive(p)[0] == _lib.LBM_EINVAL
+
+
+@pytest.mark.parametrize("prec,esz", [(64, 8), (32, 4)])
+def test_state_bytes(prec, esz):
+    p = make_params(inputs.FLAT, precision=prec)
+    nb = _lib.load().lbm_state_bytes(ctypes.byref(p))
+    # 39 planes (two 18-plane population buffers, S, phi, mu) of at least nx*ny cells
+    assert nb >= 39 * 256 * 4 * esz and nb % 256 == 0
+    big = make_params(inputs.THROUGHPUT, precision=prec)
+    nbb = _lib.load().lbm_state_bytes(ctypes.byref(big))
+    assert 39 * 16384 * 16384 * esz <= nbb < 39 * 16384 * 16384 * esz * 1.001
+
+
+def test_init_rejects_null_and_misaligned():
+    L = _lib.load()
+    p = make_params(inputs.FLAT)
+    ctx = ctypes.c_void_p()
+    assert L.lbm_init(ctypes.byref(ctx), ctypes.byref(p), None, None, None, None, None, None) == _lib.LBM_EINVAL
+    assert L.lbm_init(ctypes.byref(ctx), ctypes.byref(p), ctypes.c_void_p(0x1001),
+                      ctypes.c_void_p(0x2000), ctypes.c_void_p(0x3000), None, None, None) == _lib.LBM_EINVAL
+    assert L.lbm_init(None, ctypes.byref(p), None, None, None, None, None, None) == _lib.LBM_EINVAL
+
+
+def test_strerror_and_null_context():
+    L = _lib.load()
+    for code in (0, -1, -2, -3, -4, 7):
+        assert isinstance(L.lbm_strerror(code), bytes)
+    assert L.lbm_step(None, 1) == _lib.LBM_EINVAL
+    assert L.lbm_step_count(None) == -1
+    assert L.lbm_destroy(None) == 0
+    assert L.lbm_stream_copy(None, None, 16, None) == _lib.LBM_EINVAL

@@ -1,0 +1,292 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64: the state (pre-collision f, g and previous-step source) and the
+moments match the oracle to 1e-12 relative per field after 0, 1 and many
+steps, on periodic, walled, ragged, tiny and paper-shaped grids.
+FP32 (deviation storage): phi within 1e-5 and spurious velocity within 1e-6
+of the FP64 oracle.  Integer index work (streaming, bounce-back, periodic
+wrap, the state scatter/gather) is checked bit for bit.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import equilibrium
+import oracle
+from harness import compare_moments, compare_state, gpu_moments, gpu_sim, gpu_state, oracle_sim, rel
+from paper_2311_10827_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _case(name):
+    wl = inputs.COALESCENCE
+    if name == "flat":
+        return inputs.FLAT, inputs.flat_interface(), {}
+    if name == "drop64":
+        return inputs.DROPLET, inputs.droplet(64, 64, 16.0, 4.0, 31.7, 32.2), dict(nx=64, ny=64)
+    if name == "ragged_walls":
+        return wl, inputs.two_drops(67, 45, 10.0, 5.0, noise=1e-3), dict(nx=67, ny=45, bc_x=1, bc_y=1)
+    if name == "ragged_periodic":
+        return (inputs.ADJOINT, inputs.two_drops(131, 70, 12.0, 5.0, noise=1e-3, workload_id=5),
+                dict(nx=131, ny=70))
+    if name == "tiny_periodic":
+        return inputs.ADJOINT, inputs.two_drops(3, 5, 1.0, 2.0, noise=1e-2), dict(nx=3, ny=5)
+    if name == "tiny_walls":
+        return inputs.ADJOINT, inputs.two_drops(4, 3, 1.0, 2.0, noise=1e-2), dict(nx=4, ny=3, bc_x=1, bc_y=1)
+    if name == "one_column":
+        phi0 = np.ascontiguousarray(np.tanh((np.arange(70.0)[:, None] - 35.0) / 2.0))
+        return inputs.FLAT, phi0, dict(nx=1, ny=70, bc_x=1, bc_y=1)
+    raise KeyError(name)
+
+
+CASES = ["flat", "drop64", "ragged_walls", "ragged_periodic", "tiny_periodic", "tiny_walls", "one_column"]
+
+
+@pytest.mark.parametrize("name", CASES)
+def test_fp64_init_and_steps_match_oracle(name):
+    wl, phi0, over = _case(name)
+    say(f"[gpu] fp64 parity {name} shape={phi0.shape}")
+    g = gpu_sim(wl, phi0, 64, **over)
+    o = oracle_sim(wl, phi0, **over)
+    done = 0
+    for n in (0, 1, 9, 290):
+        g.step(n)
+        o.step(n)
+        done += n
+        cs = compare_state(gpu_state(g), o.get_state(), TOL64)
+        gm, _ = gpu_moments(g)
+        cm = compare_moments(gm, o.moments(), TOL64)
+        say(f"  step {done}: state {cs} moments {cm}")
+    assert g.step_count == done
+
+
+def test_fp64_flat_interface_long_run():
+    wl, phi0, over = _case("flat")
+    say("[gpu] fp64 flat 256x4 20000 steps")
+    g = gpu_sim(wl, phi0, 64)
+    o = oracle_sim(wl, phi0)
+    g.step(20000)
+    o.step(20000)
+    compare_state(gpu_state(g), o.get_state(), TOL64)
+    gm, d = gpu_moments(g)
+    compare_moments(gm, o.moments(), TOL64, u_floor=1e-17)
+    assert 1.4e-2 <= np.abs(gm["phi"] - phi0).max() <= 1.7e-2
+
+
+def test_fp64_coalescence_crop():
+    # 512 x 512 window of the 4096^2 two-drop field with seeded noise.
+    wl = inputs.COALESCENCE
+    x0, y0, w, h = wl.extra["crop"]
+    full = inputs.two_drops(4096, 4096, wl.extra["R"], wl.W, noise=wl.extra["noise"], workload_id=3)
+    phi0 = np.ascontiguousarray(full[y0:y0 + h, x0:x0 + w])
+    say(f"[gpu] fp64 coalescence crop {phi0.shape}")
+    g = gpu_sim(wl, phi0, 64, nx=w, ny=h)
+    o = oracle_sim(wl, phi0, nx=w, ny=h)
+    g.step(300)
+    o.step(300)
+    compare_state(gpu_state(g), o.get_state(), TOL64)
+    compare_moments(gpu_moments(g)[0], o.moments(), TOL64)
+
+
+def test_fp64_well_balanced_fixed_point():
+    wl = inputs.DROPLET
+    phi0 = inputs.droplet(48, 48, 12.0, 4.0, 23.6, 24.3)
+    prm = oracle.params_for(wl, nx=48, ny=48)
+    ps, mu0, _ = equilibrium.solve(phi0, prm.kappa, prm.beta, 1.0, -1.0)
+    say("[gpu] fp64 well-balanced fixed point 48x48")
+    g = gpu_sim(wl, ps, 64, nx=48, ny=48)
+    g.step(1000)
+    gm, d = gpu_moments(g)
+    assert np.hypot(gm["ux"], gm["uy"]).max() <= 1e-14
+    assert d["kinetic_energy"] <= 1e-26
+    assert np.abs(gm["phi"] - ps).max() <= 1e-12
+    assert np.abs(gm["mu"] - mu0).max() <= 1e-15
+
+
+@pytest.mark.parametrize("name", ["flat", "drop64"])
+def test_fp32_error_against_fp64_oracle(name):
+    # FP32 deviation storage: phi error <= 1e-5 and spurious velocity <= 1e-6.
+    wl, phi0, over = _case(name)
+    say(f"[gpu] fp32 vs oracle {name}")
+    g = gpu_sim(wl, phi0, 32, **over)
+    o = oracle_sim(wl, phi0, **over)
+    for n in (1, 199, 1800):
+        g.step(n)
+        o.step(n)
+        gm, d = gpu_moments(g)
+        om = o.moments()
+        e_phi = np.abs(gm["phi"] - om["phi"]).max()
+        e_u = max(np.abs(gm["ux"] - om["ux"]).max(), np.abs(gm["uy"] - om["uy"]).max())
+        sv = np.hypot(gm["ux"], gm["uy"]).max()
+        say(f"  step {g.step_count}: phi err {e_phi:.3e}  u err {e_u:.3e}  max|u| {sv:.3e}")
+        assert e_phi <= 1e-5 and e_u <= 1e-6 and sv <= 1e-6
+
+
+def test_fp32_well_balanced_fixed_point():
+    wl = inputs.DROPLET
+    phi0 = inputs.droplet(48, 48, 12.0, 4.0, 23.6, 24.3)
+    prm = oracle.params_for(wl, nx=48, ny=48)
+    ps, mu0, _ = equilibrium.solve(phi0, prm.kappa, prm.beta, 1.0, -1.0)
+    say("[gpu] fp32 well-balanced fixed point 48x48")
+    g = gpu_sim(wl, ps, 32, nx=48, ny=48)
+    g.step(2000)
+    gm, d = gpu_moments(g)
+    assert np.hypot(gm["ux"], gm["uy"]).max() <= 1e-6
+    assert np.abs(gm["phi"] - ps).max() <= 1e-5
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0), (1, 1)])
+def test_state_roundtrip_bit_exact(prec, bc):
+    # set_state scatters, get_state gathers (pull streaming with bounce-back):
+    # together the identity on integer codes, bit for bit.
+    nx, ny = 70, 9
+    codes = np.arange(9 * ny * nx, dtype=np.float64).reshape(9, ny, nx)
+    say(f"[gpu] roundtrip prec={prec} bc={bc}")
+    g = gpu_sim(inputs.FLAT, np.zeros((ny, nx)), prec, nx=nx, ny=ny, bc_x=bc[0], bc_y=bc[1])
+    f0 = codes + (0.0 if prec == 64 else 0.0)
+    g.set_state(f0, -codes, codes[0] * 2, step=5)
+    f, gg, Sp = gpu_state(g)
+    assert np.array_equal(f, f0) and np.array_equal(gg, -codes) and np.array_equal(Sp, codes[0] * 2)
+    assert g.step_count == 5
+    # windows wrap periodically
+    f, gg, Sp = gpu_state(g, (65, 7, 10, 5))
+    xs = (65 + np.arange(10)) % nx
+    ys = (7 + np.arange(5)) % ny
+    assert np.array_equal(f, f0[:, ys][:, :, xs]) and np.array_equal(Sp, (codes[0] * 2)[ys][:, xs])
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0), (0, 1), (1, 1)])
+def test_one_step_from_arbitrary_state(bc):
+    # Any state (not only one produced by init): load the same random
+    # pre-collision state into both sides and take one step.
+    rng = np.random.default_rng(11)
+    nx, ny = 37, 21
+    wl = inputs.ADJOINT
+    phi = inputs.two_drops(nx, ny, 6.0, 5.0, noise=1e-3)
+    o = oracle_sim(wl, phi, nx=nx, ny=ny, bc_x=bc[0], bc_y=bc[1])
+    o.step(3)
+    f, gp, Sp = o.get_state()
+    f = f + 1e-4 * rng.standard_normal(f.shape)
+    gp = gp + 1e-6 * rng.standard_normal(gp.shape)
+    Sp = Sp + 1e-6 * rng.standard_normal(Sp.shape)
+    o.set_state(f, gp, Sp).step(1)
+    say(f"[gpu] one step from arbitrary state bc={bc}")
+    g = gpu_sim(wl, phi, 64, nx=nx, ny=ny, bc_x=bc[0], bc_y=bc[1])
+    g.set_state(f, gp, Sp).step(1)
+    compare_state(gpu_state(g), o.get_state(), TOL64)
+
+
+def test_translation_invariance_bitwise():
+    wl = inputs.ADJOINT
+    phi0 = inputs.two_drops(96, 80, 12.0, 5.0, noise=1e-3)
+    say("[gpu] translation invariance")
+    a = gpu_sim(wl, phi0, 64, nx=96, ny=80).step(25)
+    b = gpu_sim(wl, np.roll(phi0, (7, 33), (0, 1)), 64, nx=96, ny=80).step(25)
+    sa, sb = gpu_state(a), gpu_state(b)
+    for x, y in zip(sa, sb):
+        assert np.array_equal(np.roll(x, (7, 33), (-2, -1)), y)
+
+
+def test_run_twice_bitwise_and_diag_reproducible():
+    wl = inputs.ADJOINT
+    phi0 = inputs.two_drops(200, 130, 30.0, 5.0, noise=1e-3)
+    say("[gpu] determinism")
+    runs = []
+    for _ in range(2):
+        g = gpu_sim(wl, phi0, 32, nx=200, ny=130, diag_every=10).step(57)
+        m, d = gpu_moments(g)
+        runs.append((gpu_state(g), m, d, g.last_diag()))
+    (s1, m1, d1, l1), (s2, m2, d2, l2) = runs
+    assert all(np.array_equal(a, b) for a, b in zip(s1, s2))
+    assert all(np.array_equal(m1[k], m2[k]) for k in m1)
+    assert d1 == d2 and l1 == l2 and l1["step"] == 50
+
+
+def test_diagnostics_match_oracle_moments_and_budget():
+    wl = inputs.ADJOINT
+    phi0 = inputs.two_drops(150, 101, 25.0, 5.0, noise=1e-3)
+    say("[gpu] diagnostics")
+    g = gpu_sim(wl, phi0, 64, nx=150, ny=101, bc_x=1)
+    o = oracle_sim(wl, phi0, nx=150, ny=101, bc_x=1)
+    g.step(40)
+    o.step(40)
+    _, d = gpu_moments(g)
+    om = o.moments()
+    _, _, Sp = o.get_state()
+    ke = 0.5 * (om["rho"] * (om["ux"] ** 2 + om["uy"] ** 2)).sum()
+    src = (1.5 * om["S"] - 0.5 * Sp).sum()
+    assert d["sum_phi"] == pytest.approx(om["phi"].sum(), rel=1e-12, abs=1e-12)
+    assert d["kinetic_energy"] == pytest.approx(ke, rel=1e-10)
+    assert d["source_sum"] == pytest.approx(src, rel=1e-9, abs=1e-18)
+    assert d["max_u"] == pytest.approx(np.hypot(om["ux"], om["uy"]).max(), rel=1e-10)
+    assert d["min_rho"] == pytest.approx(om["rho"].min(), rel=1e-13)
+    assert d["max_rho"] == pytest.approx(om["rho"].max(), rel=1e-13)
+    assert d["mu_min"] == pytest.approx(om["mu"].min(), rel=1e-10)
+    assert d["mu_max"] == pytest.approx(om["mu"].max(), rel=1e-10)
+    assert d["n_nonfinite"] == 0 and d["step"] == 40
+    # budget identity of the next step (exact up to rounding)
+    s0 = d["sum_phi"]
+    g.step(1)
+    _, d1 = gpu_moments(g)
+    assert abs(d1["sum_phi"] - (s0 - d["source_sum"])) <= 1e-13 * np.abs(om["phi"]).sum()
+
+
+def test_nonfinite_detection():
+    wl = inputs.ADJOINT
+    nx, ny = 64, 32
+    phi0 = inputs.two_drops(nx, ny, 8.0, 5.0)
+    say("[gpu] non-finite detection")
+    g = gpu_sim(wl, phi0, 64, nx=nx, ny=ny, diag_every=4)
+    f, gp, Sp = gpu_state(g)
+    f[3, 10, 20] = np.nan
+    g.set_state(f, gp, Sp)
+    from paper_2311_10827_amd._lib import LBM_ENONFINITE, LbmError
+    with pytest.raises(LbmError) as e:
+        for _ in range(3):
+            g.step(4)
+            g.last_diag()
+            g.step(1)
+    assert e.value.code == LBM_ENONFINITE
+    assert g.last_diag()["ok"] is False
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_full_size_sampled(prec):
+    # 16384^2 many-drop workload in the launch configuration the benchmark
+    # times: one and two steps, checked on sampled windows against the oracle
+    # run on each window (periodic patch, margin 3 cells per step).
+    wl = inputs.THROUGHPUT
+    say(f"[gpu] full size 16384^2 prec={prec}: generating input")
+    phi0 = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
+    g = gpu_sim(wl, phi0, prec)
+    del phi0
+    rng = np.random.default_rng(77)
+    pts = [(0, 0), (16383, 16383), (16380, 5)] + [tuple(rng.integers(0, 16384, 2)) for _ in range(5)]
+    H = 10
+    wins = [((x - H) % 16384, (y - H) % 16384, 2 * H, 2 * H) for x, y in pts]
+    before = [gpu_state(g, w) for w in wins]
+    # FP32: the GPU computes in FP32 from the same (exactly representable)
+    # stored state the FP64 oracle starts from; differences are rounding.
+    tol = TOL64 if prec == 64 else 2e-5
+    for nsteps in (1, 2):
+        g.step(1)
+        say(f"  step {g.step_count}")
+        for w, (f, gp, Sp) in zip(wins, before):
+            o = oracle.Sim(oracle.params_for(wl, nx=2 * H, ny=2 * H)).set_state(f, gp, Sp)
+            o.step(nsteps)
+            ost = o.get_state()
+            gst = gpu_state(g, w)
+            m = 3 * nsteps
+            c = (Ellipsis, slice(m, 2 * H - m), slice(m, 2 * H - m))
+            for a, b in zip(gst, ost):
+                scale = max(np.abs(b[c]).max(), 1e-30)
+                assert np.abs(a[c] - b[c]).max() <= tol * scale, (prec, nsteps, w)
