@@ -26,11 +26,12 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS & % HBM roofline, FP32 vs FP64 step; adjoint/forward step cost ratio"
 HBM_PEAK_GBPS = 8000.0
 # Algorithmic HBM bytes per lattice update of each kernel (per cell):
-#   collide-stream: 18 populations read + 18 written, phi and mu read once,
+#   collide-stream: 18 populations read + 18 written (FP32: 19, the rest
+#                   population of f as hi + lo), phi and mu read once,
 #                   previous source read and new source written;
-#   phi/mu pass:    9 populations read, phi and mu written.
-COLLIDE_BYTES = {32: (18 + 18 + 2 + 2) * 4, 64: (18 + 18 + 2 + 2) * 8}
-PHIMU_BYTES = {32: (9 + 2) * 4, 64: (9 + 2) * 8}
+#   phi/mu pass:    9 populations read (FP32: 10), phi and mu written.
+COLLIDE_BYTES = {32: (19 + 19 + 2 + 2) * 4, 64: (18 + 18 + 2 + 2) * 8}
+PHIMU_BYTES = {32: (10 + 2) * 4, 64: (9 + 2) * 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_many_drops_16384.json")
 
 
@@ -39,8 +40,13 @@ def log(*a):
 
 
 def kernel_source_hash() -> str:
-    with open(os.path.join(ROOT, "paper_2311_10827_amd", "csrc", "lbmwb.hip"), "rb") as fh:
-        return hashlib.sha256(fh.read()).hexdigest()[:16]
+    """Hash of the HIP sources (the counters are only valid for this code)."""
+    d = os.path.join(ROOT, "paper_2311_10827_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as fh:
+            h.update(name.encode() + fh.read())
+    return h.hexdigest()[:16]
 
 
 def measured_traffic(prec: int):

@@ -92,6 +92,7 @@ const int CY[Q] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
 const double WT[Q] = {4.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9, 1.0 / 9,
                       1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 const double CS2 = 1.0 / 3.0;  // c_s^2 with c = 1
+const double INV_CS2 = 3.0;    // 1/c_s^2, exact because c_s^2 = 1/3
 int opposite(int i) {
   for (int j = 0; j < Q; ++j)
     if (CX[j] == -CX[i] && CY[j] == -CY[i]) return j;
@@ -139,7 +140,7 @@ struct Sim {
     th.kappa = q.kappa;
     th.beta = q.beta;
     th.alpha = q.alpha;
-    th.tau_f = 0.5 + q.M / (CS2 * q.alpha);  // eq. mobility solved for tau_f
+    th.tau_f = 0.5 + q.M * INV_CS2 / q.alpha;  // eq. mobility solved for tau_f
     th.nu_A = q.nu_A;
     th.nu_B = q.nu_B;
     size_t n = (size_t)nx * ny;
@@ -171,8 +172,8 @@ struct Sim {
         R ax = 0.0, ay = 0.0;
         for (int i = 1; i < Q; ++i) {
           R v = psi[at(sx(x + CX[i]), sy(y + CY[i]))];
-          ax += WT[i] * CX[i] * v / CS2;
-          ay += WT[i] * CY[i] * v / CS2;
+          ax += WT[i] * CX[i] * v * INV_CS2;
+          ay += WT[i] * CY[i] * v * INV_CS2;
         }
         gx[at(x, y)] = ax;
         gy[at(x, y)] = ay;
@@ -187,7 +188,7 @@ struct Sim {
         R c = psi[at(x, y)];
         R a = 0.0;
         for (int i = 1; i < Q; ++i)
-          a += 2.0 * WT[i] * (psi[at(sx(x + CX[i]), sy(y + CY[i]))] - c) / CS2;
+          a += 2.0 * WT[i] * (psi[at(sx(x + CX[i]), sy(y + CY[i]))] - c) * INV_CS2;
         out[at(x, y)] = a;
       }
   }
@@ -203,11 +204,14 @@ struct Sim {
   }
 
   // Linear density and viscosity in phi (Sec. 2.3.2, eq. vis and the text before it).
+  // rho = rho_B + (phi - phi_B) (rho_A - rho_B) / (phi_A - phi_B), and the same for nu
   R density(R ph) const {
-    return p.rho_B + (ph - p.phi_B) * (p.rho_A - p.rho_B) / (p.phi_A - p.phi_B);
+    const double slope = (p.rho_A - p.rho_B) / (p.phi_A - p.phi_B);
+    return p.rho_B + (ph - p.phi_B) * slope;
   }
   R viscosity(R ph) const {
-    return th.nu_B + (ph - p.phi_B) * (th.nu_A - th.nu_B) / (p.phi_A - p.phi_B);
+    const R slope = (th.nu_A - th.nu_B) / (p.phi_A - p.phi_B);
+    return th.nu_B + (ph - p.phi_B) * slope;
   }
 
   // Sec. 2.3.1, eq. H_i.
@@ -220,19 +224,19 @@ struct Sim {
     for (int i = 0; i < Q; ++i) {
       // I : (c_i c_i - c_s^2 I) = |c_i|^2 - 2 c_s^2 in two dimensions
       double contraction = (double)(CX[i] * CX[i] + CY[i] * CY[i]) - 2.0 * CS2;
-      out[i] = WT[i] * s * (-1.0 + contraction / (2.0 * CS2));
+      out[i] = WT[i] * s * (-1.0 + 0.5 * contraction * INV_CS2);
     }
   }
   // Sec. 2.3.2, eq. Siu.
   R s_i(int i, R vx, R vy) const {
     R cu = CX[i] * vx + CY[i] * vy;
     R uu = vx * vx + vy * vy;
-    return WT[i] * (cu / CS2 + cu * cu / (2.0 * CS2 * CS2) - uu / (2.0 * CS2));
+    return WT[i] * (cu * INV_CS2 + 0.5 * cu * cu * INV_CS2 * INV_CS2 - 0.5 * uu * INV_CS2);
   }
   // Sec. 2.3.2, eq. G_i.
   void geq(R pp, R rh, R vx, R vy, R* out) const {
     for (int i = 0; i < Q; ++i)
-      out[i] = (i == 0 ? pp / CS2 * (WT[0] - 1.0) : pp / CS2 * WT[i]) + rh * s_i(i, vx, vy);
+      out[i] = (i == 0 ? pp * INV_CS2 * (WT[0] - 1.0) : pp * INV_CS2 * WT[i]) + rh * s_i(i, vx, vy);
   }
   // Sec. 2.3.2, eq. GGi (reading of the unbalanced parenthesis: the third
   // term is the dyad u grad(rho) contracted with c_i c_i - c_s^2 I, over c_s^2).
@@ -243,7 +247,7 @@ struct Sim {
       // (u grad rho) : (c c - c_s^2 I) = sum_ab u_a d_b rho (c_a c_b - c_s^2 delta_ab)
       R dyad = vx * rx * (CX[i] * CX[i] - CS2) + vx * ry * (CX[i] * CY[i]) +
                vy * rx * (CY[i] * CX[i]) + vy * ry * (CY[i] * CY[i] - CS2);
-      out[i] = (1.0 - 1.0 / (2.0 * tau)) * WT[i] * (ugr + cF / CS2 + dyad / CS2);
+      out[i] = (1.0 - 1.0 / (2.0 * tau)) * WT[i] * (ugr + cF * INV_CS2 + dyad * INV_CS2);
     }
   }
   // Sec. 2.3.2, macroscopic subequations: u and p from g, rho, F, grad(rho).
@@ -291,20 +295,22 @@ struct Sim {
 #pragma omp parallel for schedule(static)
     for (long k = 0; k < (long)n; ++k) {
       R eq[Q], Fn[Q], Fo[Q], ge[Q], Gi[Q];
+      const R omega_f = 1.0 / th.tau_f;  // eq. BGK multiplies the non-equilibrium part by 1/tau_f
       feq(phi[k], mu[k], eq);
       source(S[k], Fn);
       source(Sp[k], Fo);
       for (int i = 0; i < Q; ++i) {
         R fi = f[i * n + k];
         // eq. BGK with delta_t = 1 and dF/dt ~ F(t) - F(t-1)
-        fs[i * n + k] = fi - (fi - eq[i]) / th.tau_f + Fn[i] + 0.5 * (Fn[i] - Fo[i]);
+        fs[i * n + k] = fi - omega_f * (fi - eq[i]) + Fn[i] + 0.5 * (Fn[i] - Fo[i]);
       }
-      R tau_g = 0.5 + nu[k] / CS2;  // viscosity-relaxation relation, solved for tau_g
+      R tau_g = 0.5 + nu[k] * INV_CS2;  // viscosity-relaxation relation, solved for tau_g
+      R omega_g = 1.0 / tau_g;
       geq(pr[k], rho[k], ux[k], uy[k], ge);
       forcing(tau_g, ux[k], uy[k], Fx[k], Fy[k], grhx[k], grhy[k], Gi);
       for (int i = 0; i < Q; ++i) {
         R gi = g[i * n + k];
-        gs[i * n + k] = gi - (gi - ge[i]) / tau_g + Gi[i];  // eq. BGK-NS
+        gs[i * n + k] = gi - omega_g * (gi - ge[i]) + Gi[i];  // eq. BGK-NS
       }
     }
   }
@@ -433,7 +439,7 @@ void orc_chemical_potential(const orc_params* p, const double* phi, double* out)
   s.chemical_potential(v, o);
   copy_out(o, out);
 }
-double orc_tau_f(const orc_params* p) { return 0.5 + p->M / (CS2 * p->alpha); }
+double orc_tau_f(const orc_params* p) { return 0.5 + p->M * INV_CS2 / p->alpha; }
 
 // ------------------------------------------------------------- simulation
 void* orc_create(const orc_params* p) { return new Sim<double>(*p); }

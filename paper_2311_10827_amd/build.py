@@ -12,6 +12,8 @@ LIB = os.path.join(HERE, "liblbmwb.so")
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # no fused multiply-add contraction: FP64 results follow the written order
+    "-ffp-contract=off",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-I", os.path.join(ROOT, "include"),

@@ -1,0 +1,205 @@
+// Device-side building blocks shared by the kernels of liblbmwb: D2Q9
+// tables, kernel parameters, tile order, neighbour indexing, the pull gather
+// and the fixed-order diagnostic reduction.
+//
+// Population storage (one "pop buffer"), planes of the storage type T:
+//   FP64: 18 planes  f_0..f_8, g_0..g_8
+//   FP32: 19 planes  f_0(hi), f_1..f_8, g_0..g_8, f_0(lo)
+// In FP32 the rest population of the order-parameter distribution is kept as
+// an unevaluated sum hi + lo of two FP32 numbers (minus phi_ref): it is of
+// order one and changes by far less than an FP32 ulp per step, so a single
+// FP32 word would drop those changes.  All other populations are small
+// deviations from the rest equilibrium (g^eq(p=0, u=0) = 0, f^eq_i(mu=0) = 0
+// for i != 0) and keep full relative precision in one FP32 word.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <type_traits>
+
+namespace lbm {
+
+// ------------------------------------------------------------------ lattice
+// D2Q9 (Sec. 2.2, eq. eq:ci): 0 rest, 1 E, 2 N, 3 W, 4 S, 5 NE, 6 NW, 7 SW, 8 SE.
+__host__ __device__ constexpr int cx_of(int i) {
+  return (i == 1 || i == 5 || i == 8) ? 1 : (i == 3 || i == 6 || i == 7) ? -1 : 0;
+}
+__host__ __device__ constexpr int cy_of(int i) {
+  return (i == 2 || i == 5 || i == 6) ? 1 : (i == 4 || i == 7 || i == 8) ? -1 : 0;
+}
+__host__ __device__ constexpr int opp_of(int i) {
+  return i == 0 ? 0 : (i <= 4 ? ((i + 1) % 4) + 1 : ((i - 3) % 4) + 5);
+}
+// weights w_i (Sec. 2.2, after eq. H_iyang)
+__host__ __device__ constexpr double w_of(int i) {
+  return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+constexpr double CS2 = 1.0 / 3.0;   // c_s^2
+constexpr double INV_CS2 = 3.0;     // 1 / c_s^2, exact
+// Source shape of Sec. 2.3.1, eq. F_i: -1 + I:(c_i c_i - c_s^2 I)/(2 c_s^2),
+// with I:(c c - c_s^2 I) = |c|^2 - 2 c_s^2 in two dimensions.
+__host__ __device__ constexpr double src_bracket(int i) {
+  return -1.0 + 0.5 * ((double)(cx_of(i) * cx_of(i) + cy_of(i) * cy_of(i)) - 2.0 * CS2) * INV_CS2;
+}
+
+template <typename T>
+struct Store;
+template <>
+struct Store<double> {
+  static constexpr int NB = 18;  // planes per pop buffer
+};
+template <>
+struct Store<float> {
+  static constexpr int NB = 19;  // plus the low word of f_0
+};
+constexpr int LO_PLANE = 18;
+constexpr int NQ = 11;  // diagnostic quantities, in the order of lbm_diag's leading fields
+
+// Kernel parameters: geometry and the constants of the step in FP64; the
+// FP32 kernels convert them once.
+struct KP {
+  int nx, ny, pitch, bcx, bcy;
+  long long ps;                 // plane stride, elements
+  double phi_ref;               // stored offset of phi and f_0 (0 in FP64)
+  double phiA, phiB, phim;
+  double beta4;                 // 4 beta
+  double kappa, alpha;
+  double omega_f;               // 1 / tau_f
+  double rhoB, rho_slope;       // rho = rho_B + (phi - phi_B) rho_slope
+  double nuB, nu_slope;         // nu  = nu_B  + (phi - phi_B) nu_slope
+  double gx, gy;
+};
+
+// XCD-aware tile order: the hardware deals workgroups round-robin over the
+// 8 XCDs, so each XCD gets one contiguous band of tiles and neighbouring
+// tiles share that XCD's L2.  A bijection of [0, n).
+__device__ __forceinline__ int xcd_tile(int b, int n) {
+  const int X = 8;
+  const int per = n / X, rem = n % X;
+  const int xcd = b % X, local = b / X;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// Stencil neighbour: periodic wrap, or the mirrored adjacent cell across a
+// wall.  Valid for any integer v.
+__device__ __forceinline__ int stencil_idx(int v, int n, int wall) {
+  if (wall) return v < 0 ? 0 : (v >= n ? n - 1 : v);
+  int r = v % n;
+  return r < 0 ? r + n : r;
+}
+
+// Pull sources along one axis for the links arriving at v: m = source of a
+// +1 link (v-1), p = source of a -1 link (v+1); -1 marks a wall crossing.
+struct PullCols {
+  int m, p;
+};
+__device__ __forceinline__ PullCols pull_cols(int v, int n, int wall) {
+  PullCols r;
+  r.m = v > 0 ? v - 1 : (wall ? -1 : n - 1);
+  r.p = v < n - 1 ? v + 1 : (wall ? -1 : 0);
+  return r;
+}
+
+// Pre-collision populations of cell (x, y): pull streaming from the buffer,
+// half-way bounce-back (B_opp(i) at the cell itself) for links from a wall.
+template <typename T>
+struct Pops {
+  T f[9], g[9];
+  T lo;  // FP32 only: low word of f_0
+};
+
+template <bool WITH_G, typename T>
+__device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int x, int y, Pops<T>& q) {
+  const PullCols px = pull_cols(x, p.nx, p.bcx);
+  const PullCols py = pull_cols(y, p.ny, p.bcy);
+  const long long own = (long long)y * p.pitch + x;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const int cx = cx_of(i), cy = cy_of(i);
+    const int sx = cx == 1 ? px.m : (cx == -1 ? px.p : x);
+    const int sy = cy == 1 ? py.m : (cy == -1 ? py.p : y);
+    long long off;
+    int plane;
+    if (sx < 0 || sy < 0) {
+      plane = opp_of(i);
+      off = own;
+    } else {
+      plane = i;
+      off = (long long)sy * p.pitch + sx;
+    }
+    q.f[i] = B[plane * p.ps + off];
+    if (WITH_G) q.g[i] = B[(9 + plane) * p.ps + off];
+  }
+  if (std::is_same<T, float>::value) q.lo = B[LO_PLANE * p.ps + own];
+}
+
+// Store one pre-collision population so that the pull gather returns it:
+// B_i(x - c_i), or B_opp(i)(x) if the link crosses a wall.  Each buffer entry
+// is the image of exactly one (cell, direction).
+template <typename T>
+__device__ __forceinline__ void scatter(T* __restrict__ B, const KP& p, int x, int y, int plane0, int i,
+                                        T v) {
+  const PullCols px = pull_cols(x, p.nx, p.bcx);
+  const PullCols py = pull_cols(y, p.ny, p.bcy);
+  const int cx = cx_of(i), cy = cy_of(i);
+  const int sx = cx == 1 ? px.m : (cx == -1 ? px.p : x);
+  const int sy = cy == 1 ? py.m : (cy == -1 ? py.p : y);
+  if (sx < 0 || sy < 0)
+    B[(plane0 + opp_of(i)) * p.ps + (long long)y * p.pitch + x] = v;
+  else
+    B[(plane0 + i) * p.ps + (long long)sy * p.pitch + sx] = v;
+}
+
+// Split a value into an FP32 pair hi + lo.
+__device__ __forceinline__ void split2(double v, float& hi, float& lo) {
+  hi = (float)v;
+  lo = (float)(v - (double)hi);
+}
+
+// ------------------------------------------------------------ diagnostics
+struct Diag {
+  double v[NQ];
+};
+__device__ __forceinline__ void diag_identity(Diag& d) {
+  d.v[0] = d.v[1] = d.v[2] = d.v[3] = 0.0;
+  d.v[4] = INFINITY;
+  d.v[5] = -INFINITY;
+  d.v[6] = INFINITY;
+  d.v[7] = -INFINITY;
+  d.v[8] = INFINITY;
+  d.v[9] = -INFINITY;
+  d.v[10] = 0.0;
+}
+__host__ __device__ inline bool diag_is_min(int k) { return k == 4 || k == 6 || k == 8; }
+__host__ __device__ inline bool diag_is_max(int k) { return k == 3 || k == 5 || k == 7 || k == 9; }
+__device__ __forceinline__ double diag_op(int k, double a, double b) {
+  return diag_is_min(k) ? fmin(a, b) : (diag_is_max(k) ? fmax(a, b) : a + b);
+}
+
+// Fixed-order block reduction: xor butterfly inside each 64-lane
+// wavefront, then the block's waves in index order.  Bitwise reproducible.
+__device__ inline void block_reduce_write(Diag& d, double* __restrict__ out) {
+  __shared__ double red[16][NQ];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NQ; ++k) {
+    double a = d.v[k];
+#pragma unroll
+    for (int s = 32; s >= 1; s >>= 1) a = diag_op(k, a, __shfl_xor(a, s, 64));
+    d.v[k] = a;
+  }
+  if (lane == 0)
+    for (int k = 0; k < NQ; ++k) red[wave][k] = d.v[k];
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int nw = blockDim.x >> 6;
+    for (int k = 0; k < NQ; ++k) {
+      double a = red[0][k];
+      for (int w = 1; w < nw; ++w) a = diag_op(k, a, red[w][k]);
+      out[k] = a;
+    }
+  }
+}
+
+}  // namespace lbm

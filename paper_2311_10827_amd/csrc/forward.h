@@ -1,0 +1,469 @@
+// Forward kernels of one time step of the well-balanced phase-field LBM
+// (Ju et al., arXiv 2311.10827): the phi/mu stencil pass (K1) and the fused
+// collide-and-pull-stream pass (K2), plus initialisation and state I/O.
+//
+// FP64 arithmetic is written term by term in the order of the plain
+// definitions (sums over the velocity set in index order, no fused
+// multiply-add: the library is compiled with -ffp-contract=off), so the FP64
+// step is reproducible against any implementation of the same definitions in
+// that order.  The FP32 path uses difference forms that keep small
+// quantities small: stencils as differences phi(x + c) - phi(x), factored
+// double-well, and the f_0 update as an increment added to hi + lo.
+#pragma once
+#include "common.h"
+
+namespace lbm {
+
+// ---------------------------------------------------------- FP64 operators
+// Isotropic gradient (Sec. 2.3.2, eq. gradient),
+//   grad Psi = sum_{i=1..8} w_i c_i Psi(x + c_i) / c_s^2,
+// accumulated over i = 1..8 in index order (terms with c_i = 0 omitted).
+// v[dy+1][dx+1] holds Psi(x + dx, y + dy).
+__device__ __forceinline__ void grad_f64(const double (&v)[3][3], double& gx, double& gy) {
+  const double w1 = w_of(1), w5 = w_of(5);
+  double ax = (w1 * v[1][2]) * INV_CS2;     // 1 E
+  ax = ax + ((-w1) * v[1][0]) * INV_CS2;    // 3 W
+  ax = ax + (w5 * v[2][2]) * INV_CS2;       // 5 NE
+  ax = ax + ((-w5) * v[2][0]) * INV_CS2;    // 6 NW
+  ax = ax + ((-w5) * v[0][0]) * INV_CS2;    // 7 SW
+  ax = ax + (w5 * v[0][2]) * INV_CS2;       // 8 SE
+  double ay = (w1 * v[2][1]) * INV_CS2;     // 2 N
+  ay = ay + ((-w1) * v[0][1]) * INV_CS2;    // 4 S
+  ay = ay + (w5 * v[2][2]) * INV_CS2;       // 5 NE
+  ay = ay + (w5 * v[2][0]) * INV_CS2;       // 6 NW
+  ay = ay + ((-w5) * v[0][0]) * INV_CS2;    // 7 SW
+  ay = ay + ((-w5) * v[0][2]) * INV_CS2;    // 8 SE
+  gx = ax;
+  gy = ay;
+}
+
+// Isotropic Laplacian (Sec. 2.3.2, eq. Laplace),
+//   lap Psi = sum_{i=1..8} 2 w_i [Psi(x + c_i) - Psi(x)] / c_s^2, i in index order.
+__device__ __forceinline__ double lap_f64(const double (&v)[3][3]) {
+  const double a1 = 2.0 * w_of(1), a5 = 2.0 * w_of(5);
+  const double c = v[1][1];
+  double a = (a1 * (v[1][2] - c)) * INV_CS2;  // E
+  a = a + (a1 * (v[2][1] - c)) * INV_CS2;     // N
+  a = a + (a1 * (v[1][0] - c)) * INV_CS2;     // W
+  a = a + (a1 * (v[0][1] - c)) * INV_CS2;     // S
+  a = a + (a5 * (v[2][2] - c)) * INV_CS2;     // NE
+  a = a + (a5 * (v[2][0] - c)) * INV_CS2;     // NW
+  a = a + (a5 * (v[0][0] - c)) * INV_CS2;     // SW
+  a = a + (a5 * (v[0][2] - c)) * INV_CS2;     // SE
+  return a;
+}
+
+// s_i(u) of Sec. 2.3.2, eq. Siu:
+//   w_i [c.u / c_s^2 + (c.u)^2 / (2 c_s^4) - u.u / (2 c_s^2)].
+__device__ __forceinline__ double s_f64(int i, double ux, double uy, double uu) {
+  const double cu = (double)cx_of(i) * ux + (double)cy_of(i) * uy;
+  return w_of(i) * ((cu * INV_CS2 + ((0.5 * cu) * cu) * INV_CS2 * INV_CS2) - (0.5 * uu) * INV_CS2);
+}
+
+// ----------------------------------------------------------- K1: phi and mu
+// phi = sum_i f_i (Sec. 2.3.1, eq. order-parameter) on a tile plus a one-cell
+// ring, staged in LDS; then mu = 4 beta (phi - phi_A)(phi - phi_B)(phi - phi_m)
+// - kappa lap(phi) (Sec. 2.1, eq. chemical_potencial).  The dphi plane gets
+// phi - phi_ref.  FROM_INPUT: phi comes from the caller's FP64 field
+// (initialisation); then the arithmetic is FP64 whatever the storage type.
+constexpr int K1_TX = 64, K1_TY = 16;
+
+template <typename T, bool FROM_INPUT>
+__global__ __launch_bounds__(256) void k_phi_mu(const KP p, const T* __restrict__ B,
+                                                 const double* __restrict__ phi_in,
+                                                 T* __restrict__ dphi_out, T* __restrict__ mu_out,
+                                                 int ntx) {
+  using C = typename std::conditional<FROM_INPUT, double, T>::type;
+  constexpr int LW = K1_TX + 2, LH = K1_TY + 2;
+  __shared__ C s[LH * LW];
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (tile % ntx) * K1_TX, y0 = (tile / ntx) * K1_TY;
+  for (int k = threadIdx.x; k < LH * LW; k += blockDim.x) {
+    const int ly = k / LW, lx = k - ly * LW;
+    const int gx = stencil_idx(x0 + lx - 1, p.nx, p.bcx);
+    const int gy = stencil_idx(y0 + ly - 1, p.ny, p.bcy);
+    C v;
+    if (FROM_INPUT) {
+      v = (C)(phi_in[(long long)gy * p.nx + gx] - p.phi_ref);
+    } else {
+      Pops<T> q;
+      gather<false>(B, p, gx, gy, q);
+      if (std::is_same<T, double>::value) {
+        C a = q.f[0];  // sum over i in index order
+#pragma unroll
+        for (int i = 1; i < 9; ++i) a = a + q.f[i];
+        v = a;
+      } else {
+        const C s8 = ((q.f[1] + q.f[2]) + (q.f[3] + q.f[4])) + ((q.f[5] + q.f[6]) + (q.f[7] + q.f[8]));
+        v = q.f[0] + ((C)q.lo + s8);
+      }
+    }
+    s[k] = v;
+  }
+  __syncthreads();
+  const int lx = threadIdx.x % K1_TX;
+  for (int ly = threadIdx.x / K1_TX; ly < K1_TY; ly += blockDim.x / K1_TX) {
+    const int x = x0 + lx, y = y0 + ly;
+    if (x >= p.nx || y >= p.ny) continue;
+    const C* r0 = s + ly * LW + lx;  // row y-1 starting at column x-1
+    const C* r1 = r0 + LW;
+    const C* r2 = r1 + LW;
+    C mu;
+    const C c = r1[1];
+    if (std::is_same<C, double>::value) {
+      const double v[3][3] = {{(double)r0[0], (double)r0[1], (double)r0[2]},
+                              {(double)r1[0], (double)r1[1], (double)r1[2]},
+                              {(double)r2[0], (double)r2[1], (double)r2[2]}};
+      const double ph = (double)c + p.phi_ref;
+      const double lap = lap_f64(v);
+      mu = (C)((((p.beta4 * (ph - p.phiA)) * (ph - p.phiB)) * (ph - p.phim)) - p.kappa * lap);
+    } else {
+      const C axis = ((r1[2] - c) + (r1[0] - c)) + ((r2[1] - c) + (r0[1] - c));
+      const C diag = ((r2[2] - c) + (r2[0] - c)) + ((r0[2] - c) + (r0[0] - c));
+      const C lap = (C)(2.0 / 3.0) * axis + (C)(1.0 / 6.0) * diag;
+      const C dA = c + (C)(p.phi_ref - p.phiA), dB = c + (C)(p.phi_ref - p.phiB);
+      const C dm = c + (C)(p.phi_ref - p.phim);
+      mu = ((C)p.beta4 * (dA * dB)) * dm - (C)p.kappa * lap;
+    }
+    const long long o = (long long)y * p.pitch + x;
+    dphi_out[o] = (T)c;
+    mu_out[o] = (T)mu;
+  }
+}
+
+// ---------------------------------------------------- K2: collide + stream
+// Per cell: gather f_i, g_i (pull streaming with bounce-back), read the 3x3
+// neighbourhoods of phi and mu, and apply
+//   grad phi, grad mu, grad rho (Sec. 2.3.2, eq. gradient);
+//   rho, nu linear in phi (Sec. 2.3.2, eq. vis), tau_g = 1/2 + nu / c_s^2;
+//   F = -phi grad mu + G (Sec. 2.1 after eq. 6; Sec. 2.3.2 after eq. GGi);
+//   rho u = sum c_i g_i + F/2, p = c_s^2/(1-w_0)[sum_{i!=0} g_i + u.grad(rho)/2
+//     + rho s_0(u)] (Sec. 2.3.2, macroscopic subequations);
+//   S = u.grad phi; the f collision with F_i(S) + [F_i(S) - F_i(S_prev)]/2
+//     (Sec. 2.3.1, eqs. BGK, H_i, F_i; backward difference in time);
+//   the g collision with g^eq and G_i (Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi).
+// The result is written at the cell itself into the other buffer (the next
+// step's pull gather does the streaming); S replaces S_prev in place.
+enum Mode { M_STEP = 0, M_STEP_DIAG = 1, M_MOMENTS = 2, M_INIT_S = 3 };
+
+struct MomOut {
+  double *phi, *mu, *ux, *uy, *p, *rho;
+};
+
+constexpr int K2_TX = 64, K2_TY = 4;
+
+template <typename T>
+struct Nbhd {
+  T ph[3][3], mu[3][3];  // [dy+1][dx+1]
+};
+
+template <typename T>
+__device__ __forceinline__ void load_nbhd(const KP& p, const T* __restrict__ dphi,
+                                          const T* __restrict__ mupl, int x, int y, Nbhd<T>& n) {
+  const int xs[3] = {stencil_idx(x - 1, p.nx, p.bcx), x, stencil_idx(x + 1, p.nx, p.bcx)};
+  const int ys[3] = {stencil_idx(y - 1, p.ny, p.bcy), y, stencil_idx(y + 1, p.ny, p.bcy)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const long long r = (long long)ys[a] * p.pitch;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+      n.ph[a][b] = dphi[r + xs[b]];
+      n.mu[a][b] = mupl[r + xs[b]];
+    }
+  }
+}
+
+// Macroscopic quantities of one cell, in FP64 (for moments and diagnostics).
+struct CellOut {
+  double phi, mu, ux, uy, p, rho, S, Sp;
+};
+
+// FP64 cell update, plain-definition order.  Writes the post-collision
+// populations to fo/go when WRITE is set.
+template <bool WRITE>
+__device__ __forceinline__ void cell_f64(const KP& p, const Pops<double>& q, const Nbhd<double>& n,
+                                         double Sp, double (&fo)[9], double (&go)[9], CellOut& out) {
+  double rho3[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) rho3[a][b] = p.rhoB + (n.ph[a][b] - p.phiB) * p.rho_slope;
+  const double phi = n.ph[1][1], mu = n.mu[1][1], rho = rho3[1][1];
+  const double nu = p.nuB + (phi - p.phiB) * p.nu_slope;
+  double gpx, gpy, gmx, gmy, grx, gry;
+  grad_f64(n.ph, gpx, gpy);
+  grad_f64(n.mu, gmx, gmy);
+  grad_f64(rho3, grx, gry);
+  const double Fx = (-phi) * gmx + p.gx;
+  const double Fy = (-phi) * gmy + p.gy;
+  const double* g = q.g;
+  const double mx = ((((g[1] - g[3]) + g[5]) - g[6]) - g[7]) + g[8];
+  const double my = ((((g[2] - g[4]) + g[5]) + g[6]) - g[7]) - g[8];
+  double snz = g[1];
+#pragma unroll
+  for (int i = 2; i < 9; ++i) snz = snz + g[i];
+  const double ux = (mx + 0.5 * Fx) / rho;
+  const double uy = (my + 0.5 * Fy) / rho;
+  const double uu = ux * ux + uy * uy;
+  const double s0 = w_of(0) * (0.0 - (0.5 * uu) * INV_CS2);
+  const double pr = (CS2 / (1.0 - w_of(0))) * ((snz + 0.5 * (ux * grx + uy * gry)) + rho * s0);
+  const double S = ux * gpx + uy * gpy;
+  out = CellOut{phi, mu, ux, uy, pr, rho, S, Sp};
+  if (!WRITE) return;
+  // order-parameter population (Sec. 2.3.1, eqs. BGK, H_i, F_i)
+  const double* f = q.f;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double feq = i == 0 ? phi - ((1.0 - w_of(0)) * p.alpha) * mu : (w_of(i) * p.alpha) * mu;
+    const double Fn = (w_of(i) * S) * src_bracket(i);
+    const double Fo = (w_of(i) * Sp) * src_bracket(i);
+    fo[i] = ((f[i] - p.omega_f * (f[i] - feq)) + Fn) + 0.5 * (Fn - Fo);
+  }
+  // hydrodynamic population (Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi)
+  const double tau = 0.5 + nu * INV_CS2;
+  const double wg = 1.0 / tau;
+  const double kG = 1.0 - 1.0 / (2.0 * tau);
+  const double ugr = ux * grx + uy * gry;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const double cx = cx_of(i), cy = cy_of(i);
+    const double geq = (i == 0 ? (pr * INV_CS2) * (w_of(0) - 1.0) : (pr * INV_CS2) * w_of(i)) +
+                       rho * s_f64(i, ux, uy, uu);
+    const double cF = cx * Fx + cy * Fy;
+    const double a = (double)(cx_of(i) * cx_of(i)) - CS2;
+    const double b = (double)(cx_of(i) * cy_of(i));
+    const double d = (double)(cy_of(i) * cy_of(i)) - CS2;
+    const double dyad = (((ux * grx) * a + (ux * gry) * b) + (uy * grx) * b) + (uy * gry) * d;
+    const double Gi = (kG * w_of(i)) * ((ugr + cF * INV_CS2) + dyad * INV_CS2);
+    go[i] = (g[i] - wg * (g[i] - geq)) + Gi;
+  }
+}
+
+// FP32 cell update in difference forms.  fo[0] receives hi, fo_lo the low word.
+template <bool WRITE>
+__device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, const Nbhd<float>& n,
+                                         float Sp, float (&fo)[9], float& fo_lo, float (&go)[9],
+                                         CellOut& out) {
+  const float third = (float)(1.0 / 3.0), twelfth = (float)(1.0 / 12.0);
+  const auto& ph = n.ph;
+  const auto& m = n.mu;
+  const float gpx = third * (ph[1][2] - ph[1][0]) + twelfth * ((ph[2][2] - ph[2][0]) + (ph[0][2] - ph[0][0]));
+  const float gpy = third * (ph[2][1] - ph[0][1]) + twelfth * ((ph[2][2] - ph[0][2]) + (ph[2][0] - ph[0][0]));
+  const float gmx = third * (m[1][2] - m[1][0]) + twelfth * ((m[2][2] - m[2][0]) + (m[0][2] - m[0][0]));
+  const float gmy = third * (m[2][1] - m[0][1]) + twelfth * ((m[2][2] - m[0][2]) + (m[2][0] - m[0][0]));
+  const float dph = ph[1][1];  // phi - phi_ref
+  const float phi = dph + (float)p.phi_ref;
+  const float mu = m[1][1];
+  const float dB = dph + (float)(p.phi_ref - p.phiB);
+  const float drho = (float)p.rho_slope;
+  const float rho = (float)p.rhoB + dB * drho;
+  const float grx = drho * gpx, gry = drho * gpy;
+  const float Fx = (float)p.gx - phi * gmx, Fy = (float)p.gy - phi * gmy;
+  const float* g = q.g;
+  const float mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
+  const float my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
+  const float gnz = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
+  const float irho = 1.0f / rho;
+  const float ux = (mx + 0.5f * Fx) * irho, uy = (my + 0.5f * Fy) * irho;
+  const float uu = ux * ux + uy * uy;
+  const float ugr = ux * grx + uy * gry;
+  const float pr = 0.6f * (gnz + 0.5f * ugr - (float)(2.0 / 3.0) * rho * uu);
+  const float S = ux * gpx + uy * gpy;
+  const float* f = q.f;
+  const float s8 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
+  out.phi = p.phi_ref + ((double)f[0] + ((double)q.lo + (double)s8));
+  out.mu = mu;
+  out.ux = ux;
+  out.uy = uy;
+  out.p = pr;
+  out.rho = rho;
+  out.S = S;
+  out.Sp = Sp;
+  if (!WRITE) return;
+  const float src = 1.5f * S - 0.5f * Sp;
+  const float wf = (float)p.omega_f;
+  const float am = (float)p.alpha * mu;
+  // f_0 - f_0^eq = -(s8 - (5/9) alpha mu) exactly, since phi = f_0 + s8; add the
+  // small increment to hi + lo (FastTwoSum keeps the rounding error in lo).
+  const float inc0 = wf * (s8 - (float)(5.0 / 9.0) * am) + (float)(w_of(0) * src_bracket(0)) * src;
+  const float t = q.lo + inc0;
+  const float hi = f[0] + t;
+  fo[0] = hi;
+  fo_lo = t - (hi - f[0]);
+#pragma unroll
+  for (int i = 1; i < 9; ++i)
+    fo[i] = f[i] + wf * ((float)w_of(i) * am - f[i]) + (float)(w_of(i) * src_bracket(i)) * src;
+  const float tau = 0.5f + 3.0f * ((float)p.nuB + dB * (float)p.nu_slope);
+  const float wg = 1.0f / tau;
+  const float kG = 1.0f - 0.5f * wg;
+  const float ge0 = -(float)(5.0 / 3.0) * pr - (float)(2.0 / 3.0) * rho * uu;
+  go[0] = g[0] + wg * (ge0 - g[0]);
+  const float p3 = 3.0f * pr, ruu = 1.5f * rho * uu;
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const float cu = (float)cx_of(i) * ux + (float)cy_of(i) * uy;
+    const float cF = (float)cx_of(i) * Fx + (float)cy_of(i) * Fy;
+    const float cr = (float)cx_of(i) * grx + (float)cy_of(i) * gry;
+    const float w = (float)w_of(i);
+    const float geq = w * (p3 + rho * (cu * (3.0f + 4.5f * cu)) - ruu);
+    const float Gi = kG * 3.0f * w * (cF + cu * cr);
+    go[i] = g[i] + wg * (geq - g[i]) + Gi;
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(256) void k_collide(const KP p, const T* __restrict__ Bin,
+                                                  T* __restrict__ Bout, T* __restrict__ Spl,
+                                                  const T* __restrict__ dphi,
+                                                  const T* __restrict__ mupl, MomOut mo,
+                                                  double* __restrict__ partials, int ntx) {
+  constexpr bool DIAG = MODE == M_STEP_DIAG || MODE == M_MOMENTS;
+  constexpr bool WRITE = MODE == M_STEP || MODE == M_STEP_DIAG;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int x = (tile % ntx) * K2_TX + (threadIdx.x & (K2_TX - 1));
+  const int y = (tile / ntx) * K2_TY + threadIdx.x / K2_TX;
+  const bool valid = x < p.nx && y < p.ny;
+  Diag dg;
+  if (DIAG) diag_identity(dg);
+  if (valid) {
+    const long long o = (long long)y * p.pitch + x;
+    Pops<T> q;
+    gather<true>(Bin, p, x, y, q);
+    Nbhd<T> nb;
+    load_nbhd(p, dphi, mupl, x, y, nb);
+    const T Sp = Spl[o];
+    T fo[9], go[9];
+    T lo = 0;
+    CellOut c;
+    if constexpr (std::is_same<T, double>::value)
+      cell_f64<WRITE>(p, q, nb, Sp, fo, go, c);
+    else
+      cell_f32<WRITE>(p, q, nb, Sp, fo, lo, go, c);
+    if (WRITE) {
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        Bout[i * p.ps + o] = fo[i];
+        Bout[(9 + i) * p.ps + o] = go[i];
+      }
+      if constexpr (std::is_same<T, float>::value) Bout[LO_PLANE * p.ps + o] = lo;
+      Spl[o] = (T)c.S;
+    }
+    if (MODE == M_INIT_S) Spl[o] = (T)c.S;
+    if (MODE == M_MOMENTS) {
+      const long long k = (long long)y * p.nx + x;
+      if (mo.phi) mo.phi[k] = c.phi;
+      if (mo.mu) mo.mu[k] = c.mu;
+      if (mo.ux) mo.ux[k] = c.ux;
+      if (mo.uy) mo.uy[k] = c.uy;
+      if (mo.p) mo.p[k] = c.p;
+      if (mo.rho) mo.rho[k] = c.rho;
+    }
+    if (DIAG) {
+      const bool fin = isfinite(c.phi) && isfinite(c.mu) && isfinite(c.ux) && isfinite(c.uy) &&
+                       isfinite(c.p);
+      dg.v[0] = c.phi;
+      dg.v[1] = 1.5 * c.S - 0.5 * c.Sp;
+      dg.v[2] = 0.5 * c.rho * (c.ux * c.ux + c.uy * c.uy);
+      dg.v[3] = sqrt(c.ux * c.ux + c.uy * c.uy);
+      dg.v[4] = dg.v[5] = c.rho;
+      dg.v[6] = dg.v[7] = c.mu;
+      dg.v[8] = dg.v[9] = c.phi;
+      dg.v[10] = fin ? 0.0 : 1.0;
+    }
+  }
+  if (DIAG) block_reduce_write(dg, partials + (long long)tile * NQ);
+}
+
+__global__ __launch_bounds__(256) void k_reduce_diag(const double* __restrict__ partials, int n,
+                                                      double* __restrict__ out) {
+  Diag d;
+  diag_identity(d);
+  for (int b = threadIdx.x; b < n; b += blockDim.x)
+    for (int k = 0; k < NQ; ++k) d.v[k] = diag_op(k, d.v[k], partials[(long long)b * NQ + k]);
+  block_reduce_write(d, out);
+}
+
+// ------------------------------------------------------------ state I/O
+template <typename T>
+__device__ __forceinline__ void put_f0(T* __restrict__ B, const KP& p, int x, int y, double v) {
+  // the rest population never streams, so it is stored at the cell itself
+  const long long own = (long long)y * p.pitch + x;
+  if constexpr (std::is_same<T, float>::value) {
+    float hi, lo;
+    split2(v, hi, lo);
+    B[own] = hi;
+    B[LO_PLANE * p.ps + own] = lo;
+  } else {
+    B[own] = v;
+  }
+}
+
+// Initial populations (time 0): f = f^eq(phi0, mu0) (Sec. 2.3.1, eq. H_i) and
+// g = g^eq(p = 0, u0) (Sec. 2.3.2, eqs. G_i, Siu), in FP64; mu0 comes from
+// k_phi_mu<FROM_INPUT>.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init_pops(const KP p, T* __restrict__ B,
+                                                    const double* __restrict__ phi0,
+                                                    const double* __restrict__ ux0,
+                                                    const double* __restrict__ uy0,
+                                                    const T* __restrict__ mupl) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= (long long)p.nx * p.ny) return;
+  const int y = (int)(k / p.nx), x = (int)(k - (long long)y * p.nx);
+  const double ph = phi0[k];
+  const double mu = (double)mupl[(long long)y * p.pitch + x];
+  put_f0<T>(B, p, x, y, (ph - ((1.0 - w_of(0)) * p.alpha) * mu) - p.phi_ref);
+  for (int i = 1; i < 9; ++i) scatter<T>(B, p, x, y, 0, i, (T)((w_of(i) * p.alpha) * mu));
+  const double ux = ux0 ? ux0[k] : 0.0, uy = uy0 ? uy0[k] : 0.0;
+  const double rho = p.rhoB + (ph - p.phiB) * p.rho_slope;
+  const double uu = ux * ux + uy * uy;
+  for (int i = 0; i < 9; ++i) scatter<T>(B, p, x, y, 9, i, (T)(rho * s_f64(i, ux, uy, uu)));
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_set_state(const KP p, T* __restrict__ B, T* __restrict__ Spl,
+                                                    const double* __restrict__ f,
+                                                    const double* __restrict__ g,
+                                                    const double* __restrict__ Sp) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = (long long)p.nx * p.ny;
+  if (k >= n) return;
+  const int y = (int)(k / p.nx), x = (int)(k - (long long)y * p.nx);
+  put_f0<T>(B, p, x, y, f[k] - p.phi_ref);
+  for (int i = 1; i < 9; ++i) scatter<T>(B, p, x, y, 0, i, (T)f[i * n + k]);
+  for (int i = 0; i < 9; ++i) scatter<T>(B, p, x, y, 9, i, (T)g[i * n + k]);
+  Spl[(long long)y * p.pitch + x] = (T)Sp[k];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_get_state(const KP p, const T* __restrict__ B,
+                                                    const T* __restrict__ Spl, int x0, int y0,
+                                                    int w, int h, double* __restrict__ f,
+                                                    double* __restrict__ g,
+                                                    double* __restrict__ Sp) {
+  const long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long n = (long long)w * h;
+  if (k >= n) return;
+  const int wy = (int)(k / w), wx = (int)(k - (long long)wy * w);
+  const int x = (x0 + wx) % p.nx, y = (y0 + wy) % p.ny;
+  Pops<T> q;
+  gather<true>(B, p, x, y, q);
+  if (f) {
+    double f0 = (double)q.f[0];
+    if constexpr (std::is_same<T, float>::value) f0 = f0 + (double)q.lo;
+    f[k] = f0 + p.phi_ref;
+    for (int i = 1; i < 9; ++i) f[i * n + k] = (double)q.f[i];
+  }
+  if (g)
+    for (int i = 0; i < 9; ++i) g[i * n + k] = (double)q.g[i];
+  if (Sp) Sp[k] = (double)Spl[(long long)y * p.pitch + x];
+}
+
+__global__ __launch_bounds__(256) void k_copy(float4* __restrict__ dst, const float4* __restrict__ src,
+                                               long long n) {
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x)
+    dst[k] = src[k];
+}
+
+}  // namespace lbm

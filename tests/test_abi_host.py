@@ -72,11 +72,13 @@ def test_sigma_W_must_be_positive():
 def test_state_bytes(prec, esz):
     p = make_params(inputs.FLAT, precision=prec)
     nb = _lib.load().lbm_state_bytes(ctypes.byref(p))
-    # 39 planes (two 18-plane population buffers, S, phi, mu) of at least nx*ny cells
-    assert nb >= 39 * 256 * 4 * esz and nb % 256 == 0
+    # two population buffers (18 planes in FP64, 19 in FP32: f_0 as hi + lo),
+    # plus S, phi, mu, each plane at least nx*ny cells
+    planes = 39 if prec == 64 else 41
+    assert nb >= planes * 256 * 4 * esz and nb % 256 == 0
     big = make_params(inputs.THROUGHPUT, precision=prec)
     nbb = _lib.load().lbm_state_bytes(ctypes.byref(big))
-    assert 39 * 16384 * 16384 * esz <= nbb < 39 * 16384 * 16384 * esz * 1.001
+    assert planes * 16384 * 16384 * esz <= nbb < planes * 16384 * 16384 * esz * 1.001
 
 
 def test_init_rejects_null_and_misaligned():
