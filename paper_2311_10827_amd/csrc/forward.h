@@ -374,13 +374,20 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* __restrict
   if (DIAG) block_reduce_write(dg, partials + (long long)tile * NQ);
 }
 
-__global__ __launch_bounds__(256) void k_reduce_diag(const double* __restrict__ partials, int n,
-                                                      double* __restrict__ out) {
+// Two-level fixed-order reduction of n partials: block b of the first pass
+// reduces the contiguous chunk [b*chunk, (b+1)*chunk) into out[b]; a single
+// block then reduces those.  The assignment of partials to lanes depends
+// only on n, so the result is bitwise reproducible.
+constexpr int RED_BLOCKS = 1024;
+__global__ __launch_bounds__(256) void k_reduce_diag(const double* __restrict__ partials, long long n,
+                                                      long long chunk, double* __restrict__ out) {
   Diag d;
   diag_identity(d);
-  for (int b = threadIdx.x; b < n; b += blockDim.x)
-    for (int k = 0; k < NQ; ++k) d.v[k] = diag_op(k, d.v[k], partials[(long long)b * NQ + k]);
-  block_reduce_write(d, out);
+  const long long b0 = (long long)blockIdx.x * chunk;
+  const long long b1 = b0 + chunk < n ? b0 + chunk : n;
+  for (long long b = b0 + threadIdx.x; b < b1; b += blockDim.x)
+    for (int k = 0; k < NQ; ++k) d.v[k] = diag_op(k, d.v[k], partials[b * NQ + k]);
+  block_reduce_write(d, out + (long long)blockIdx.x * NQ);
 }
 
 // ------------------------------------------------------------ state I/O

@@ -35,6 +35,7 @@ struct lbm_ctx {
   int64_t step;
   int ntx1, nty1, ntx2, nty2;
   double* partials;
+  double* red_mid;      // [RED_BLOCKS][NQ]: first-level reduction results
   double* diag_dev;     // [2][NQ]: fused step diagnostics, moments diagnostics
   double* diag_host;    // pinned [2][NQ]
   int64_t diag_step;
@@ -110,7 +111,7 @@ Layout layout_of(const lbm_params* p) {
   L.ntx2 = (p->nx + K2_TX - 1) / K2_TX;
   L.nty2 = (p->ny + K2_TY - 1) / K2_TY;
   const size_t nparts = (size_t)L.ntx2 * L.nty2;
-  L.ws_bytes = round_up((nparts * NQ + 2 * NQ) * sizeof(double), 256);
+  L.ws_bytes = round_up((nparts * NQ + (RED_BLOCKS + 2) * NQ) * sizeof(double), 256);
   return L;
 }
 
@@ -160,8 +161,14 @@ int launch_collide(lbm_ctx* c, MomOut mo) {
 }
 
 int launch_reduce(lbm_ctx* c, int slot) {
-  hipLaunchKernelGGL(k_reduce_diag, dim3(1), dim3(256), 0, c->stream, c->partials,
-                     c->ntx2 * c->nty2, c->diag_dev + slot * NQ);
+  const long long n = (long long)c->ntx2 * c->nty2;
+  const long long chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
+  const long long nb = (n + chunk - 1) / chunk;
+  hipLaunchKernelGGL(k_reduce_diag, dim3((unsigned)nb), dim3(256), 0, c->stream, c->partials, n, chunk,
+                     c->red_mid);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL(k_reduce_diag, dim3(1), dim3(256), 0, c->stream, c->red_mid, nb, nb,
+                     c->diag_dev + slot * NQ);
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -332,7 +339,8 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   c->ntx2 = L.ntx2;
   c->nty2 = L.nty2;
   c->partials = reinterpret_cast<double*>(c->ws);
-  c->diag_dev = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
+  c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
+  c->diag_dev = c->red_mid + (size_t)RED_BLOCKS * NQ;
   c->diag_pending = c->diag_seen = c->nonfinite = false;
   c->timing = false;
   KP& k = c->kp;

@@ -285,17 +285,18 @@ def test_full_size_sampled(prec):
     # FP32 differences are rounding of quantities of the size each field has
     # where it is active, so they are scaled by the field's largest magnitude
     # over all sampled windows (bulk windows alone hold FP64 rounding residue).
-    floors = [max(np.abs(st[k]).max() for st in before) for k in range(3)]
     for nsteps in (1, 2):
         g.step(1)
         say(f"  step {g.step_count}")
-        for w, (f, gp, Sp) in zip(wins, before):
+        m = 3 * nsteps
+        c = (Ellipsis, slice(m, 2 * H - m), slice(m, 2 * H - m))
+        ref = []
+        for f, gp, Sp in before:
             o = oracle.Sim(oracle.params_for(wl, nx=2 * H, ny=2 * H)).set_state(f, gp, Sp)
-            o.step(nsteps)
-            ost = o.get_state()
+            ref.append(o.step(nsteps).get_state())
+        floors = [max(np.abs(st[k][c]).max() for st in ref) for k in range(3)]
+        for w, ost in zip(wins, ref):
             gst = gpu_state(g, w)
-            m = 3 * nsteps
-            c = (Ellipsis, slice(m, 2 * H - m), slice(m, 2 * H - m))
             for a, b, fl in zip(gst, ost, floors):
                 scale = max(np.abs(b[c]).max(), 1e-30 if prec == 64 else fl)
                 assert np.abs(a[c] - b[c]).max() <= tol * scale, (prec, nsteps, w)
