@@ -70,9 +70,11 @@ enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
  *                  populations, and phi, mu mirrored across the wall in the
  *                  finite-difference stencils (the paper's tests are periodic).
  *   precision      64: populations stored and updated in FP64.
- *                  32: populations stored and updated in FP32, the rest
- *                      population of f held as a deviation from
- *                      (phi_A + phi_B) / 2; diagnostics stay FP64.
+ *                  32: populations stored and updated in FP32; the rest
+ *                      population of f, of order one, is held as an
+ *                      unevaluated pair of FP32 words (hi + lo) offset by
+ *                      (phi_A + phi_B) / 2, the others are small deviations
+ *                      from the rest equilibrium; diagnostics stay FP64.
  *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
  *                  diagnostic pass every k steps (see lbm_step).
  */
@@ -205,6 +207,57 @@ int lbm_kernel_times(lbm_ctx* ctx, double* ms_phi_mu, double* ms_collide, int64_
  * `stream` with a plain streaming kernel (device pointers, 16-byte aligned,
  * non-overlapping). */
 int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Checkpoints.  A snapshot is the raw current state (one population buffer
+ * and the previous-step source plane, in the storage precision): restoring
+ * it reproduces the following steps bit for bit.  dst/src: device buffers of
+ * lbm_snapshot_bytes(ctx) bytes.  lbm_restore also sets the step counter.
+ * ---------------------------------------------------------------------- */
+size_t lbm_snapshot_bytes(const lbm_ctx* ctx);
+int lbm_snapshot(lbm_ctx* ctx, void* dst);
+int lbm_restore(lbm_ctx* ctx, const void* src, int64_t step);
+/* One step from snapshot src into snapshot dst (distinct, 256-byte aligned
+ * device buffers), without touching the context's own state or step counter.
+ * dst equals what lbm_step followed by lbm_snapshot would give, bit for bit.
+ * Lets a caller recompute a segment of states without copies. */
+int lbm_step_into(lbm_ctx* ctx, const void* src, void* dst);
+
+/* ------------------------------------------------------------------------
+ * Adjoint (reverse mode) of the step.  The paper defines the forward step
+ * only (Sec. 2.3); these functions give the exact transpose of its Jacobian.
+ *
+ * The state at time n is s_n = (f, g, S_prev): pre-collision populations and
+ * the previous-step source.  An adjoint lambda has the same layout as
+ * lbm_get_state's outputs packed together: 19 dense planes [ny][nx]
+ * (f_0..f_8, g_0..g_8, S_prev) in the storage precision (double for
+ * precision 64, float for 32), device memory.  Arithmetic is FP64.
+ *
+ * Parameter gradients accumulate in the adjoint workspace for
+ * theta = (kappa, beta, alpha, tau_f, nu_A, nu_B), each taken as independent
+ * (tau_f = 1/2 + M/(c_s^2 alpha) and tau_g = 1/2 + nu/c_s^2 relate them to
+ * M and the relaxation times).
+ * ---------------------------------------------------------------------- */
+
+/* Bytes of the adjoint workspace (7 planes plus parameter partials). */
+size_t lbm_adjoint_workspace_bytes(const lbm_params* p);
+/* Attach a device workspace (256-byte aligned) and zero the parameter
+ * gradient.  Required before the other adjoint calls (else LBM_ESTATE). */
+int lbm_adjoint_attach(lbm_ctx* ctx, void* adj_workspace);
+/* state: a snapshot of s_n (lbm_snapshot / lbm_step_into).  Map
+ * lam_in = dL/ds_{n+1} to lam_out = dL/ds_n and add dL/dtheta of this step.
+ * lam_in and lam_out must not overlap.  The context's own populations are
+ * not touched (its phi and mu planes are overwritten). */
+int lbm_adjoint_step(lbm_ctx* ctx, const void* state, const void* lam_in, void* lam_out);
+/* state: a snapshot of s_0 made by lbm_init from phi0 with no initial
+ * velocity (else LBM_ESTATE).  Map lam0 = dL/ds_0 to dphi0 = dL/dphi0
+ * (device FP64 [ny][nx]) and add dL/dtheta of the initialisation.
+ * scratch: a device buffer of the adjoint's size, distinct from lam0. */
+int lbm_adjoint_init(lbm_ctx* ctx, const void* state, const double* phi0, const void* lam0,
+                     void* scratch, double* dphi0);
+/* Copy the accumulated dL/dtheta to out[6] (host; synchronises) and, if
+ * reset != 0, zero it. */
+int lbm_adjoint_theta(lbm_ctx* ctx, double* out, int reset);
 
 /* Release the context's host resources (not the caller's buffers). */
 int lbm_destroy(lbm_ctx* ctx);

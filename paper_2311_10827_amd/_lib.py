@@ -19,7 +19,9 @@ SYMBOLS = (
     "lbm_derive", "lbm_state_bytes", "lbm_workspace_bytes", "lbm_init", "lbm_step",
     "lbm_step_count", "lbm_moments", "lbm_last_diag", "lbm_get_state", "lbm_set_state",
     "lbm_timing", "lbm_kernel_times", "lbm_stream_copy", "lbm_destroy", "lbm_strerror",
-    "lbm_last_error",
+    "lbm_last_error", "lbm_snapshot_bytes", "lbm_snapshot", "lbm_restore",
+    "lbm_adjoint_workspace_bytes", "lbm_adjoint_attach", "lbm_adjoint_step", "lbm_adjoint_init",
+    "lbm_adjoint_theta", "lbm_step_into",
 )
 
 
@@ -111,6 +113,24 @@ def load() -> ctypes.CDLL:
     L.lbm_strerror.restype = ctypes.c_char_p
     L.lbm_last_error.argtypes = [vp]
     L.lbm_last_error.restype = ctypes.c_char_p
+    L.lbm_snapshot_bytes.argtypes = [vp]
+    L.lbm_snapshot_bytes.restype = ctypes.c_size_t
+    L.lbm_snapshot.argtypes = [vp, vp]
+    L.lbm_snapshot.restype = ctypes.c_int
+    L.lbm_restore.argtypes = [vp, vp, i64]
+    L.lbm_restore.restype = ctypes.c_int
+    L.lbm_adjoint_workspace_bytes.argtypes = [P]
+    L.lbm_adjoint_workspace_bytes.restype = ctypes.c_size_t
+    L.lbm_adjoint_attach.argtypes = [vp, vp]
+    L.lbm_adjoint_attach.restype = ctypes.c_int
+    L.lbm_step_into.argtypes = [vp, vp, vp]
+    L.lbm_step_into.restype = ctypes.c_int
+    L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp]
+    L.lbm_adjoint_step.restype = ctypes.c_int
+    L.lbm_adjoint_init.argtypes = [vp, vp, vp, vp, vp, vp]
+    L.lbm_adjoint_init.restype = ctypes.c_int
+    L.lbm_adjoint_theta.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.lbm_adjoint_theta.restype = ctypes.c_int
     _lib = L
     return L
 

@@ -311,10 +311,11 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
   }
 }
 
+// Spin holds S_prev of the current step; Spout receives S (they may be the
+// same plane: each cell reads and then writes only its own entry).
 template <typename T, int MODE>
-__global__ __launch_bounds__(256) void k_collide(const KP p, const T* __restrict__ Bin,
-                                                  T* __restrict__ Bout, T* __restrict__ Spl,
-                                                  const T* __restrict__ dphi,
+__global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bout, const T* Spin,
+                                                  T* Spout, const T* __restrict__ dphi,
                                                   const T* __restrict__ mupl, MomOut mo,
                                                   double* __restrict__ partials, int ntx) {
   constexpr bool DIAG = MODE == M_STEP_DIAG || MODE == M_MOMENTS;
@@ -331,7 +332,7 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* __restrict
     gather<true>(Bin, p, x, y, q);
     Nbhd<T> nb;
     load_nbhd(p, dphi, mupl, x, y, nb);
-    const T Sp = Spl[o];
+    const T Sp = Spin[o];
     T fo[9], go[9];
     T lo = 0;
     CellOut c;
@@ -346,9 +347,9 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* __restrict
         Bout[(9 + i) * p.ps + o] = go[i];
       }
       if constexpr (std::is_same<T, float>::value) Bout[LO_PLANE * p.ps + o] = lo;
-      Spl[o] = (T)c.S;
+      Spout[o] = (T)c.S;
     }
-    if (MODE == M_INIT_S) Spl[o] = (T)c.S;
+    if (MODE == M_INIT_S) Spout[o] = (T)c.S;
     if (MODE == M_MOMENTS) {
       const long long k = (long long)y * p.nx + x;
       if (mo.phi) mo.phi[k] = c.phi;

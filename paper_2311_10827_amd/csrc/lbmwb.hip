@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "adjoint.h"
 #include "forward.h"
 #include "lbmwb.h"
 
@@ -44,6 +45,11 @@ struct lbm_ctx {
   bool timing;
   std::vector<hipEvent_t> tev;  // three events per timed step
   std::string err;
+  bool u0_zero;         // lbm_init got no initial velocity
+  // adjoint workspace (lbm_adjoint_attach)
+  char* adj;
+  double* th_part;      // [tiles][NTH] parameter-gradient partials
+  double* th_out;       // [NTH]
 };
 
 namespace {
@@ -97,6 +103,17 @@ struct Layout {
   int ntx1, nty1, ntx2, nty2;
 };
 
+constexpr int ADJ_PLANES = 7;
+
+size_t adj_plane_bytes(const lbm_params* p) {
+  return round_up((size_t)p->nx * p->ny * (p->precision == 32 ? 4 : 8), 256);
+}
+
+size_t adj_bytes(const lbm_params* p) {
+  const size_t tiles = (size_t)((p->nx + K2_TX - 1) / K2_TX) * ((p->ny + K2_TY - 1) / K2_TY);
+  return ADJ_PLANES * adj_plane_bytes(p) + round_up((tiles + 1) * NTH * sizeof(double), 256);
+}
+
 Layout layout_of(const lbm_params* p) {
   Layout L;
   L.esz = p->precision == 32 ? 4 : 8;
@@ -143,21 +160,32 @@ T* mu_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + 2); }
 
 unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
+// A "state" is a pop buffer (NB planes) plus an S_prev plane.  The context's
+// own state is its current pop buffer with the shared S plane; a snapshot
+// holds NB + 1 consecutive planes in the same layout.
 template <typename T>
-int launch_phi_mu(lbm_ctx* c) {
-  hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp,
-                     popbuf<T>(c, c->cur), nullptr, dphi_plane<T>(c), mu_plane<T>(c), c->ntx1);
+int launch_phi_mu(lbm_ctx* c, const T* B) {
+  hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, B,
+                     nullptr, dphi_plane<T>(c), mu_plane<T>(c), c->ntx1);
   LAUNCHCHK(c);
   return LBM_OK;
 }
+template <typename T>
+int launch_phi_mu(lbm_ctx* c) {
+  return launch_phi_mu<T>(c, popbuf<T>(c, c->cur));
+}
 
 template <typename T, int MODE>
-int launch_collide(lbm_ctx* c, MomOut mo) {
-  hipLaunchKernelGGL((k_collide<T, MODE>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream, c->kp,
-                     popbuf<T>(c, c->cur), popbuf<T>(c, c->cur ^ 1), S_plane<T>(c), dphi_plane<T>(c),
-                     mu_plane<T>(c), mo, c->partials, c->ntx2);
+int launch_collide(lbm_ctx* c, MomOut mo, const T* Bin, T* Bout, const T* Sin, T* Sout) {
+  hipLaunchKernelGGL((k_collide<T, MODE>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream, c->kp, Bin,
+                     Bout, Sin, Sout, dphi_plane<T>(c), mu_plane<T>(c), mo, c->partials, c->ntx2);
   LAUNCHCHK(c);
   return LBM_OK;
+}
+template <typename T, int MODE>
+int launch_collide(lbm_ctx* c, MomOut mo) {
+  return launch_collide<T, MODE>(c, mo, popbuf<T>(c, c->cur), popbuf<T>(c, c->cur ^ 1), S_plane<T>(c),
+                                 S_plane<T>(c));
 }
 
 int launch_reduce(lbm_ctx* c, int slot) {
@@ -298,6 +326,80 @@ int set_state_impl(lbm_ctx* c, const double* f, const double* g, const double* S
   return LBM_OK;
 }
 
+template <typename T>
+AdjWork<T> adj_work(lbm_ctx* c) {
+  const size_t pb = adj_plane_bytes(&c->p);
+  T* q[ADJ_PLANES];
+  for (int k = 0; k < ADJ_PLANES; ++k) q[k] = reinterpret_cast<T*>(c->adj + k * pb);
+  return AdjWork<T>{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
+}
+
+template <typename T>
+const T* snap_S(const lbm_ctx* c, const T* snap) {
+  return snap + (size_t)Store<T>::NB * c->kp.ps;
+}
+
+template <typename T>
+int step_into_impl(lbm_ctx* c, const T* src, T* dst) {
+  int r = launch_phi_mu<T>(c, src);
+  if (r) return r;
+  return launch_collide<T, M_STEP>(c, MomOut{}, src, dst, snap_S(c, src), const_cast<T*>(snap_S(c, dst)));
+}
+
+template <typename T>
+int adjoint_step_impl(lbm_ctx* c, const T* state, const T* lam_in, T* lam_out) {
+  int r = launch_phi_mu<T>(c, state);
+  if (r) return r;
+  const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
+  const AdjWork<T> w = adj_work<T>(c);
+  hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state,
+                     snap_S(c, state), dphi_plane<T>(c), mu_plane<T>(c), lam_in, lam_out, w, c->th_part,
+                     c->ntx2);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL(ka_mu<T>, dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), w, c->th_part,
+                     c->ntx2);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL((ka_phi<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c),
+                     lam_in, lam_out, w, c->ntx2);
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+template <typename T>
+int adjoint_init_impl(lbm_ctx* c, const T* state, const double* phi0, const T* lam0, T* scratch,
+                      double* dphi0) {
+  int r = launch_phi_mu<T>(c, state);
+  if (r) return r;
+  const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
+  const AdjWork<T> w = adj_work<T>(c);
+  hipLaunchKernelGGL((ka_local<T, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state,
+                     snap_S(c, state), dphi_plane<T>(c), mu_plane<T>(c), lam0, scratch, w, c->th_part,
+                     c->ntx2);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL(ka_mu<T>, dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), w, c->th_part,
+                     c->ntx2);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL((ka_phi<T, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), lam0,
+                     scratch, w, c->ntx2);
+  LAUNCHCHK(c);
+  // mu0 = mu(phi0) into the mu plane
+  hipLaunchKernelGGL((k_phi_mu<T, true>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, nullptr,
+                     phi0, dphi_plane<T>(c), mu_plane<T>(c), c->ntx1);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL(ki_local<T>, dim3(nb), dim3(256), 0, c->stream, c->kp, phi0, mu_plane<T>(c), lam0,
+                     scratch, w, c->th_part, c->ntx2);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL(ki_phi<T>, dim3(nb), dim3(256), 0, c->stream, c->kp, phi0, w, dphi0, c->th_part,
+                     c->ntx2);
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+size_t snapshot_bytes(const lbm_ctx* c) {
+  const size_t nb = c->prec == 64 ? Store<double>::NB : Store<float>::NB;
+  return (nb + 1) * (size_t)c->kp.ps * c->esz;
+}
+
 }  // namespace
 
 extern "C" {
@@ -342,6 +444,9 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
   c->diag_dev = c->red_mid + (size_t)RED_BLOCKS * NQ;
   c->diag_pending = c->diag_seen = c->nonfinite = false;
+  c->u0_zero = ux0 == nullptr && uy0 == nullptr;
+  c->adj = nullptr;
+  c->th_part = c->th_out = nullptr;
   c->timing = false;
   KP& k = c->kp;
   k.nx = p->nx;
@@ -470,6 +575,93 @@ int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream) {
   hipLaunchKernelGGL(k_copy, dim3((unsigned)blocks), dim3(256), 0, static_cast<hipStream_t>(stream),
                      static_cast<float4*>(dst), static_cast<const float4*>(src), n);
   return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EHIP;
+}
+
+size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
+  if (validate(p, nullptr) != LBM_OK) return 0;
+  return adj_bytes(p);
+}
+
+int lbm_adjoint_attach(lbm_ctx* c, void* adj_workspace) {
+  if (!c || !adj_workspace || ((uintptr_t)adj_workspace & 255)) return LBM_EINVAL;
+  c->adj = static_cast<char*>(adj_workspace);
+  c->th_part = reinterpret_cast<double*>(c->adj + ADJ_PLANES * adj_plane_bytes(&c->p));
+  const long long tiles = (long long)c->ntx2 * c->nty2;
+  c->th_out = c->th_part + tiles * NTH;
+  hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, c->stream, c->th_part, (tiles + 1) * NTH);
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+int lbm_step_into(lbm_ctx* c, const void* src, void* dst) {
+  if (!c || !src || !dst || src == dst) return LBM_EINVAL;
+  if (((uintptr_t)src & 255) || ((uintptr_t)dst & 255)) return LBM_EINVAL;
+  return c->prec == 64 ? step_into_impl<double>(c, static_cast<const double*>(src), static_cast<double*>(dst))
+                       : step_into_impl<float>(c, static_cast<const float*>(src), static_cast<float*>(dst));
+}
+
+int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out) {
+  if (!c || !state || !lam_in || !lam_out || lam_in == lam_out) return LBM_EINVAL;
+  if ((uintptr_t)state & 255) return LBM_EINVAL;
+  if (!c->adj) return LBM_ESTATE;
+  return c->prec == 64
+             ? adjoint_step_impl<double>(c, static_cast<const double*>(state), static_cast<const double*>(lam_in),
+                                         static_cast<double*>(lam_out))
+             : adjoint_step_impl<float>(c, static_cast<const float*>(state), static_cast<const float*>(lam_in),
+                                        static_cast<float*>(lam_out));
+}
+
+int lbm_adjoint_init(lbm_ctx* c, const void* state, const double* phi0, const void* lam0, void* scratch,
+                     double* dphi0) {
+  if (!c || !state || !phi0 || !lam0 || !scratch || !dphi0 || lam0 == scratch) return LBM_EINVAL;
+  if ((uintptr_t)state & 255) return LBM_EINVAL;
+  if (!c->adj || !c->u0_zero) return LBM_ESTATE;
+  return c->prec == 64
+             ? adjoint_init_impl<double>(c, static_cast<const double*>(state), phi0,
+                                         static_cast<const double*>(lam0), static_cast<double*>(scratch), dphi0)
+             : adjoint_init_impl<float>(c, static_cast<const float*>(state), phi0, static_cast<const float*>(lam0),
+                                        static_cast<float*>(scratch), dphi0);
+}
+
+int lbm_adjoint_theta(lbm_ctx* c, double* out, int reset) {
+  if (!c || !out) return LBM_EINVAL;
+  if (!c->adj) return LBM_ESTATE;
+  const long long tiles = (long long)c->ntx2 * c->nty2;
+  hipLaunchKernelGGL(k_sum_theta, dim3(1), dim3(256), 0, c->stream, c->th_part, tiles, c->th_out);
+  LAUNCHCHK(c);
+  HIPCHK(c, hipMemcpyAsync(out, c->th_out, NTH * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (reset) {
+    hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, c->stream, c->th_part, tiles * NTH);
+    LAUNCHCHK(c);
+  }
+  return LBM_OK;
+}
+
+size_t lbm_snapshot_bytes(const lbm_ctx* c) { return c ? snapshot_bytes(c) : 0; }
+
+int lbm_snapshot(lbm_ctx* c, void* dst) {
+  if (!c || !dst) return LBM_EINVAL;
+  const size_t pb = (size_t)c->kp.ps * c->esz;
+  const size_t nb = c->prec == 64 ? Store<double>::NB : Store<float>::NB;
+  char* base = c->state + (size_t)c->cur * nb * pb;
+  HIPCHK(c, hipMemcpyAsync(dst, base, nb * pb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(static_cast<char*>(dst) + nb * pb, c->state + 2 * nb * pb, pb,
+                           hipMemcpyDeviceToDevice, c->stream));
+  return LBM_OK;
+}
+
+int lbm_restore(lbm_ctx* c, const void* src, int64_t step) {
+  if (!c || !src || step < 0) return LBM_EINVAL;
+  const size_t pb = (size_t)c->kp.ps * c->esz;
+  const size_t nb = c->prec == 64 ? Store<double>::NB : Store<float>::NB;
+  char* base = c->state + (size_t)c->cur * nb * pb;
+  HIPCHK(c, hipMemcpyAsync(base, src, nb * pb, hipMemcpyDeviceToDevice, c->stream));
+  HIPCHK(c, hipMemcpyAsync(c->state + 2 * nb * pb, static_cast<const char*>(src) + nb * pb, pb,
+                           hipMemcpyDeviceToDevice, c->stream));
+  c->step = step;
+  c->nonfinite = false;
+  return LBM_OK;
 }
 
 int lbm_destroy(lbm_ctx* c) {

@@ -54,6 +54,10 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _storage_dtype(precision: int):
+    return torch.float64 if precision == 64 else torch.float32
+
+
 class Sim:
     """One simulation context on one GPU."""
 
@@ -153,6 +157,57 @@ class Sim:
         check(self.L.lbm_kernel_times(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
               "lbm_kernel_times", self.ctx)
         return a.value, b.value, n.value
+
+    # -- snapshots (raw state) ----------------------------------------------
+
+    def snapshot_bytes(self) -> int:
+        return int(self.L.lbm_snapshot_bytes(self.ctx))
+
+    def new_snapshot(self) -> torch.Tensor:
+        return torch.empty(self.snapshot_bytes(), dtype=torch.uint8, device=self.device)
+
+    def snapshot(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        out = self.new_snapshot() if out is None else out
+        check(self.L.lbm_snapshot(self.ctx, _ptr(out)), "lbm_snapshot", self.ctx)
+        return out
+
+    def restore(self, snap: torch.Tensor, step: int) -> "Sim":
+        check(self.L.lbm_restore(self.ctx, _ptr(snap), int(step)), "lbm_restore", self.ctx)
+        return self
+
+    def step_into(self, src: torch.Tensor, dst: torch.Tensor) -> None:
+        check(self.L.lbm_step_into(self.ctx, _ptr(src), _ptr(dst)), "lbm_step_into", self.ctx)
+
+    # -- adjoint -------------------------------------------------------------
+    def enable_adjoint(self) -> None:
+        if getattr(self, "adj_ws", None) is not None:
+            return
+        nb = self.L.lbm_adjoint_workspace_bytes(ctypes.byref(self.p))
+        self.adj_ws = torch.empty(nb, dtype=torch.uint8, device=self.device)
+        check(self.L.lbm_adjoint_attach(self.ctx, _ptr(self.adj_ws)), "lbm_adjoint_attach", self.ctx)
+
+    def new_adjoint(self) -> torch.Tensor:
+        """Zeroed adjoint of a state: 19 planes (f_0..f_8, g_0..g_8, S_prev)."""
+        return torch.zeros((19,) + self.shape, dtype=_storage_dtype(self.p.precision), device=self.device)
+
+    def adjoint_step(self, state: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor) -> None:
+        check(self.L.lbm_adjoint_step(self.ctx, _ptr(state), _ptr(lam_in), _ptr(lam_out)),
+              "lbm_adjoint_step", self.ctx)
+
+    def adjoint_init(self, state0: torch.Tensor, phi0: torch.Tensor, lam0: torch.Tensor,
+                     scratch: torch.Tensor) -> torch.Tensor:
+        phi0 = _dev_f64(phi0, self.shape, self.device)
+        out = torch.empty(self.shape, dtype=torch.float64, device=self.device)
+        check(self.L.lbm_adjoint_init(self.ctx, _ptr(state0), _ptr(phi0), _ptr(lam0), _ptr(scratch),
+                                      _ptr(out)), "lbm_adjoint_init", self.ctx)
+        self._keep_phi0 = phi0
+        return out
+
+    def adjoint_theta(self, reset: bool = True):
+        """dL/d(kappa, beta, alpha, tau_f, nu_A, nu_B) accumulated so far."""
+        buf = (ctypes.c_double * 6)()
+        check(self.L.lbm_adjoint_theta(self.ctx, buf, int(bool(reset))), "lbm_adjoint_theta", self.ctx)
+        return list(buf)
 
 
 def stream_copy(dst: torch.Tensor, src: torch.Tensor) -> None:
