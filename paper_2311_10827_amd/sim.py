@@ -72,7 +72,9 @@ class Sim:
         if nb == 0 or nw == 0:
             raise _lib.LbmError(_lib.LBM_EINVAL, "lbm_state_bytes")
         with torch.cuda.device(self.device):
-            self.state = torch.empty(nb, dtype=torch.uint8, device=self.device)
+            # zeroed so that the padding between rows and planes (never written
+            # by the kernels) is defined and raw snapshots compare bytewise
+            self.state = torch.zeros(nb, dtype=torch.uint8, device=self.device)
             self.workspace = torch.empty(nw, dtype=torch.uint8, device=self.device)
             self.stream = torch.cuda.current_stream(self.device)
             phi0 = _dev_f64(phi0, self.shape, self.device)
@@ -164,7 +166,7 @@ class Sim:
         return int(self.L.lbm_snapshot_bytes(self.ctx))
 
     def new_snapshot(self) -> torch.Tensor:
-        return torch.empty(self.snapshot_bytes(), dtype=torch.uint8, device=self.device)
+        return torch.zeros(self.snapshot_bytes(), dtype=torch.uint8, device=self.device)
 
     def snapshot(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = self.new_snapshot() if out is None else out

@@ -153,7 +153,8 @@ def test_step_into_equals_step_bitwise(prec):
     c = sim.snapshot()
     assert torch.equal(b, c)
     sim.restore(s0, 0).step(2)
-    assert torch.equal(sim.snapshot(), c)
+    d = sim.snapshot()
+    assert torch.equal(d, c)
 
 
 def _fd_setup():
