@@ -162,6 +162,61 @@ def cpu_baseline(wl, seconds: float):
     }
 
 
+def adjoint_leg(nsteps: int, K: int):
+    """Inverse-problem gradient on the 1024^2 two-drop workload (FP32): the
+    adjoint step's cost, including its share of the checkpoint recompute,
+    relative to a forward step."""
+    import torch
+    from paper_2311_10827_amd import inputs
+    from paper_2311_10827_amd.adjoint import misfit, params_from_theta, rollout
+    from paper_2311_10827_amd.sim import Sim, derive, make_params
+
+    wl = inputs.ADJOINT
+    base = make_params(wl, precision=32)
+    d = derive(base)
+    theta = [d["kappa"], d["beta"], base.M, d["tau_f"], d["tau_gA"], d["tau_gB"]]
+    phi0 = inputs.two_drops(wl.nx, wl.ny, wl.extra["R"], wl.W, workload_id=5)
+    s1, s2 = inputs.rng_for(5).uniform(0.5, 2.0, size=2)
+    hidden = list(theta)
+    hidden[0] *= s1
+    hidden[1] *= s1          # sigma scaled by s1 at fixed W
+    hidden[2] *= s2          # M scaled by s2
+    log(f"[bench] adjoint: target with hidden (sigma, M) x ({s1:.3f}, {s2:.3f})")
+    tgt = Sim(params_from_theta(base, hidden), phi0).step(nsteps).moments(diag=False)["phi"]
+    # forward step time of the same workload
+    sim = Sim(params_from_theta(base, theta), phi0)
+    sim.step(20)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(nsteps)
+    e1.record(sim.stream)
+    torch.cuda.synchronize()
+    t_fwd = e0.elapsed_time(e1) / nsteps
+    sim.close()
+    del sim
+    log(f"[bench] adjoint: rollout {nsteps} steps, checkpoint every {K} (one warm-up gradient, "
+        "then the timed one: buffers come from torch's caching allocator)")
+    for _ in range(2):
+        ph = torch.from_numpy(phi0).cuda().requires_grad_(True)
+        th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
+        stats = {}
+        L = misfit(rollout(ph, th, base, nsteps, K, stats), tgt)
+        L.backward()
+    t_bwd = stats["backward_s"] * 1e3 / nsteps
+    return {
+        "workload": "adjoint_1024: 1024x1024 two drops R 100, density ratio 100, FP32, "
+                    f"{nsteps} steps, checkpoint every {K}",
+        "forward_ms_per_step": round(t_fwd, 5),
+        "adjoint_ms_per_step_incl_recompute": round(t_bwd, 5),
+        "ratio": round(t_bwd / t_fwd, 3),
+        "loss": float(L.detach()),
+        "dL_dtheta": dict(zip(("kappa", "beta", "M", "tau_f", "tau_gA", "tau_gB"),
+                              [float(v) for v in th.grad])),
+        "dL_dphi0_norm": float(ph.grad.norm()),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,6 +228,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-K", type=int, default=100)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
@@ -196,6 +254,7 @@ def main():
     del phi0_dev
     torch.cuda.empty_cache()
     copy_gbps = None if args.no_copy else stream_copy_probe(dev)
+    adj = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K)
     cpu = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds)
 
     out = {
@@ -229,7 +288,8 @@ def main():
             "phi_mu_GBps": r64["phi_mu_GBps"], "step_GBps_alg": r64["step_GBps_alg"],
         },
         "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),
-        "adjoint_forward_ratio": None,
+        "adjoint_forward_ratio": None if adj is None else adj["ratio"],
+        "adjoint": adj,
         "diag_after": r32["diag_after"],
     }
     print(json.dumps(out), flush=True)

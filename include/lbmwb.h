@@ -209,19 +209,22 @@ int lbm_kernel_times(lbm_ctx* ctx, double* ms_phi_mu, double* ms_collide, int64_
 int lbm_stream_copy(void* dst, const void* src, size_t bytes, void* stream);
 
 /* ------------------------------------------------------------------------
- * Checkpoints.  A snapshot is the raw current state (one population buffer
- * and the previous-step source plane, in the storage precision): restoring
- * it reproduces the following steps bit for bit.  dst/src: device buffers of
- * lbm_snapshot_bytes(ctx) bytes.  lbm_restore also sets the step counter.
+ * Checkpoints.  A snapshot holds the raw state (one population buffer and
+ * the previous-step source plane, in the storage precision) plus two scratch
+ * planes for that state's phi and mu: restoring it reproduces the following
+ * steps bit for bit.  dst/src: device buffers of lbm_snapshot_bytes(ctx)
+ * bytes, 256-byte aligned.  lbm_restore also sets the step counter.
  * ---------------------------------------------------------------------- */
+#define LBM_SNAPSHOT_HAS_PHI_MU 1
 size_t lbm_snapshot_bytes(const lbm_ctx* ctx);
 int lbm_snapshot(lbm_ctx* ctx, void* dst);
 int lbm_restore(lbm_ctx* ctx, const void* src, int64_t step);
-/* One step from snapshot src into snapshot dst (distinct, 256-byte aligned
- * device buffers), without touching the context's own state or step counter.
- * dst equals what lbm_step followed by lbm_snapshot would give, bit for bit.
+/* One step from snapshot src into snapshot dst (distinct buffers), without
+ * touching the context's own state or step counter.  The state in dst equals
+ * what lbm_step followed by lbm_snapshot gives, bit for bit; src's phi and mu
+ * planes are left holding the phi and mu of src (LBM_SNAPSHOT_HAS_PHI_MU).
  * Lets a caller recompute a segment of states without copies. */
-int lbm_step_into(lbm_ctx* ctx, const void* src, void* dst);
+int lbm_step_into(lbm_ctx* ctx, void* src, void* dst);
 
 /* ------------------------------------------------------------------------
  * Adjoint (reverse mode) of the step.  The paper defines the forward step
@@ -246,9 +249,17 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p);
 int lbm_adjoint_attach(lbm_ctx* ctx, void* adj_workspace);
 /* state: a snapshot of s_n (lbm_snapshot / lbm_step_into).  Map
  * lam_in = dL/ds_{n+1} to lam_out = dL/ds_n and add dL/dtheta of this step.
- * lam_in and lam_out must not overlap.  The context's own populations are
- * not touched (its phi and mu planes are overwritten). */
-int lbm_adjoint_step(lbm_ctx* ctx, const void* state, const void* lam_in, void* lam_out);
+ * lam_in and lam_out must not overlap.  flags: LBM_SNAPSHOT_HAS_PHI_MU if the
+ * snapshot's phi/mu planes are valid (it was the source of lbm_step_into),
+ * else 0 and they are recomputed into it. */
+int lbm_adjoint_step(lbm_ctx* ctx, void* state, const void* lam_in, void* lam_out, int flags);
+/* One checkpoint segment of the backward pass: snaps[0] holds s_k; the
+ * other L - 1 snapshots receive s_{k+1}..s_{k+L-1} (lbm_step_into), then the
+ * L adjoint steps run in reverse from lam = dL/ds_{k+L}, ping-ponging with
+ * tmp.  *which = 0 if dL/ds_k ends in lam, 1 if in tmp.  snaps: host array of
+ * L distinct device snapshot pointers. */
+int lbm_adjoint_segment(lbm_ctx* ctx, void* const* snaps, int L, void* lam, void* tmp,
+                        int* which);
 /* state: a snapshot of s_0 made by lbm_init from phi0 with no initial
  * velocity (else LBM_ESTATE).  Map lam0 = dL/ds_0 to dphi0 = dL/dphi0
  * (device FP64 [ny][nx]) and add dL/dtheta of the initialisation.

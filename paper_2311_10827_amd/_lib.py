@@ -13,6 +13,7 @@ LIB_PATH = os.path.join(HERE, "liblbmwb.so")
 
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4
 PERIODIC, WALL = 0, 1
+SNAPSHOT_HAS_PHI_MU = 1
 
 # Every symbol include/lbmwb.h declares.
 SYMBOLS = (
@@ -21,7 +22,7 @@ SYMBOLS = (
     "lbm_timing", "lbm_kernel_times", "lbm_stream_copy", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_snapshot_bytes", "lbm_snapshot", "lbm_restore",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint_attach", "lbm_adjoint_step", "lbm_adjoint_init",
-    "lbm_adjoint_theta", "lbm_step_into",
+    "lbm_adjoint_theta", "lbm_step_into", "lbm_adjoint_segment",
 )
 
 
@@ -125,8 +126,11 @@ def load() -> ctypes.CDLL:
     L.lbm_adjoint_attach.restype = ctypes.c_int
     L.lbm_step_into.argtypes = [vp, vp, vp]
     L.lbm_step_into.restype = ctypes.c_int
-    L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp]
+    L.lbm_adjoint_step.argtypes = [vp, vp, vp, vp, ctypes.c_int]
     L.lbm_adjoint_step.restype = ctypes.c_int
+    L.lbm_adjoint_segment.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int, vp, vp,
+                                      ctypes.POINTER(ctypes.c_int)]
+    L.lbm_adjoint_segment.restype = ctypes.c_int
     L.lbm_adjoint_init.argtypes = [vp, vp, vp, vp, vp, vp]
     L.lbm_adjoint_init.restype = ctypes.c_int
     L.lbm_adjoint_theta.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]

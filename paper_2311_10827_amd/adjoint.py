@@ -78,11 +78,8 @@ class _Rollout(torch.autograd.Function):
         snaps = [sim.new_snapshot() for _ in range(min(K, nsteps))]
         for seg, s0 in reversed(list(enumerate(range(0, nsteps, K)))):
             L = min(K, nsteps - s0)
-            states = [ckpt[seg]] + snaps[1:L]
-            for k in range(1, L):
-                sim.step_into(states[k - 1], states[k])
-            for k in reversed(range(L)):
-                sim.adjoint_step(states[k], lam, other)
+            # recompute the segment's states and walk it backwards in one call
+            if sim.adjoint_segment([ckpt[seg]] + snaps[1:L], lam, other) == 1:
                 lam, other = other, lam
         dphi0 = sim.adjoint_init(ckpt[0], phi0, lam, other)
         g6 = sim.adjoint_theta(reset=True)

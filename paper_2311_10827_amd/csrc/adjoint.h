@@ -15,11 +15,11 @@
 //       of the collision and of u, p, S, F, rho, nu.  The g adjoint is local
 //       and written directly; lambda for phi, mu, grad phi and grad mu goes to
 //       work planes.
-//   KA2 (per cell): lambda_mu += G^T lambda_{grad mu} (transposed isotropic
-//       gradient), plus the kappa and beta partials.
-//   KA3 (per cell): lambda_phi += G^T lambda_{grad phi} + psi''(phi) lambda_mu
-//       - kappa L^T lambda_mu, then lambda_f_i = (1 - 1/tau_f) lambda_{f*_i}
-//       + lambda_phi (phi = sum_i f_i).
+//   KA2 (per tile, LDS): lambda_mu += G^T lambda_{grad mu} (transposed
+//       isotropic gradient) on the tile and a one-cell ring, then per cell
+//       lambda_phi += G^T lambda_{grad phi} + psi''(phi) lambda_mu
+//       - kappa L^T lambda_mu and lambda_f_i = (1 - 1/tau_f) lambda_{f*_i}
+//       + lambda_phi (phi = sum_i f_i); kappa and beta partials.
 // Transposed stencils enumerate, for each direction, the cells whose
 // neighbour (periodic wrap or wall mirror) is the target cell, so walls get
 // the exact transpose.  Arithmetic is FP64; lambda planes are stored in the
@@ -53,22 +53,40 @@ __device__ __forceinline__ int preimages(int v, int c, int n, int wall, int (&ou
   return k;
 }
 
+// An axis has a single preimage per direction when it is periodic or the
+// cell does not touch a wall along it; then the preimage is v - c, wrapped.
+__device__ __forceinline__ bool single_pre(int v, int n, int wall) {
+  return !wall || (v >= 1 && v <= n - 2);
+}
+__device__ __forceinline__ int pre1(int v, int c, int n) {
+  const int r = v - c;
+  return r < 0 ? r + n : (r >= n ? r - n : r);
+}
+
 // (G^T w)(v): transposed isotropic gradient of a 2-vector field w = (wx, wy)
 // stored as dense planes [ny][nx].
-template <typename T>
-__device__ __forceinline__ double grad_T(const KP& p, const T* __restrict__ wx, const T* __restrict__ wy,
-                                         int x, int y) {
-  double acc = 0.0;
+template <typename A = double, typename T>
+__device__ __forceinline__ A grad_T(const KP& p, const T* __restrict__ wx, const T* __restrict__ wy, int x,
+                                    int y) {
+  A acc = A(0);
+  if (single_pre(x, p.nx, p.bcx) && single_pre(y, p.ny, p.bcy)) {
+#pragma unroll
+    for (int d = 1; d < 9; ++d) {
+      const long long k = (long long)pre1(y, cy_of(d), p.ny) * p.nx + pre1(x, cx_of(d), p.nx);
+      acc += A(INV_CS2 * w_of(d)) * (A(cx_of(d)) * A(wx[k]) + A(cy_of(d)) * A(wy[k]));
+    }
+    return acc;
+  }
 #pragma unroll
   for (int d = 1; d < 9; ++d) {
     int px[2], py[2];
     const int nxp = preimages(x, cx_of(d), p.nx, p.bcx, px);
     const int nyp = preimages(y, cy_of(d), p.ny, p.bcy, py);
-    const double k3 = INV_CS2 * w_of(d);
+    const A k3 = A(INV_CS2 * w_of(d));
     for (int a = 0; a < nyp; ++a)
       for (int b = 0; b < nxp; ++b) {
         const long long k = (long long)py[a] * p.nx + px[b];
-        acc += k3 * ((double)cx_of(d) * (double)wx[k] + (double)cy_of(d) * (double)wy[k]);
+        acc += k3 * (A(cx_of(d)) * A(wx[k]) + A(cy_of(d)) * A(wy[k]));
       }
   }
   return acc;
@@ -78,6 +96,13 @@ __device__ __forceinline__ double grad_T(const KP& p, const T* __restrict__ wx, 
 template <typename T>
 __device__ __forceinline__ double lap_T(const KP& p, const T* __restrict__ w, int x, int y) {
   double acc = 0.0;
+  if (single_pre(x, p.nx, p.bcx) && single_pre(y, p.ny, p.bcy)) {
+#pragma unroll
+    for (int d = 1; d < 9; ++d)
+      acc += (2.0 * INV_CS2 * w_of(d)) *
+             (double)w[(long long)pre1(y, cy_of(d), p.ny) * p.nx + pre1(x, cx_of(d), p.nx)];
+    return acc - (2.0 * INV_CS2 * (1.0 - w_of(0))) * (double)w[(long long)y * p.nx + x];
+  }
 #pragma unroll
   for (int d = 1; d < 9; ++d) {
     int px[2], py[2];
@@ -144,6 +169,8 @@ struct AdjWork {
 // ------------------------------------------------------------------ KA1
 // INIT: the map is s_0 -> S_prev(0) = S(s_0) only (no collision, no
 // streaming); the seed is lambda of S_prev(0) and lambda_f*, lambda_g* = 0.
+// Arithmetic in the storage type (FP64 for precision 64, FP32 for 32, like
+// the forward step it differentiates); parameter partials in FP64.
 template <typename T, bool INIT>
 __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict__ B,
                                                  const T* __restrict__ Spl,
@@ -152,6 +179,7 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
                                                  const T* __restrict__ lam_in, T* __restrict__ lam_out,
                                                  AdjWork<T> w, double* __restrict__ th_part,
                                                  int ntx) {
+  using C = T;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x = (tile % ntx) * K2_TX + (threadIdx.x & (K2_TX - 1));
   const int y = (tile / ntx) * K2_TY + threadIdx.x / K2_TX;
@@ -159,63 +187,62 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
   if (x < p.nx && y < p.ny) {
     const long long n = (long long)p.nx * p.ny;
     const long long kd = (long long)y * p.nx + x;
-    const long long o = (long long)y * p.pitch + x;
-    // ---- forward recompute at this cell (FP64)
+    const C half = C(0.5), one = C(1.0), three = C(3.0);
+    // ---- forward recompute at this cell
     Pops<T> q;
     gather<true>(B, p, x, y, q);
     Nbhd<T> nb;
     load_nbhd(p, dphi, mupl, x, y, nb);
-    double ph3[3][3], mu3[3][3];
+    const C phi_ref = C(p.phi_ref);
+    C ph3[3][3];
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        ph3[a][b] = (double)nb.ph[a][b] + p.phi_ref;
-        mu3[a][b] = (double)nb.mu[a][b];
-      }
-    double f[9], g[9];
+      for (int b = 0; b < 3; ++b) ph3[a][b] = nb.ph[a][b] + phi_ref;
+    const auto& mu3 = nb.mu;
+    C f[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      f[i] = (double)q.f[i];
-      g[i] = (double)q.g[i];
-    }
-    if constexpr (std::is_same<T, float>::value) f[0] += (double)q.lo;
-    f[0] += p.phi_ref;
-    const double phi = ph3[1][1], mu = mu3[1][1];
-    double gpx, gpy, gmx, gmy;
-    grad_fwd(ph3, gpx, gpy);
-    grad_fwd(mu3, gmx, gmy);
-    const double rs = p.rho_slope;
-    const double grx = rs * gpx, gry = rs * gpy;
-    const double dB = phi - p.phiB;
-    const double rho = p.rhoB + dB * rs;
-    const double nu = p.nuB + dB * p.nu_slope;
-    const double tau = 0.5 + INV_CS2 * nu;
-    const double wg = 1.0 / tau, kG = 1.0 - 0.5 * wg;
-    const double Fx = p.gx - phi * gmx, Fy = p.gy - phi * gmy;
-    const double mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
-    const double my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
-    const double ux = (mx + 0.5 * Fx) / rho, uy = (my + 0.5 * Fy) / rho;
-    const double uu = ux * ux + uy * uy;
-    const double snz = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
-    const double s0 = -(2.0 / 3.0) * uu;  // s_0(u) = w_0 (-u.u / (2 c_s^2))
-    const double C06 = CS2 / (1.0 - w_of(0));
-    const double pr = C06 * (snz + 0.5 * (ux * grx + uy * gry) + rho * s0);
+    for (int i = 0; i < 9; ++i) f[i] = q.f[i];
+    if constexpr (std::is_same<T, float>::value) f[0] += q.lo;
+    f[0] += phi_ref;
+    const C* g = q.g;
+    const C phi = ph3[1][1], mu = mu3[1][1];
+    const C k3 = C(1.0 / 3.0), k12 = C(1.0 / 12.0);
+    const C gpx = k3 * (ph3[1][2] - ph3[1][0]) + k12 * ((ph3[2][2] - ph3[2][0]) + (ph3[0][2] - ph3[0][0]));
+    const C gpy = k3 * (ph3[2][1] - ph3[0][1]) + k12 * ((ph3[2][2] - ph3[0][2]) + (ph3[2][0] - ph3[0][0]));
+    const C gmx = k3 * (mu3[1][2] - mu3[1][0]) + k12 * ((mu3[2][2] - mu3[2][0]) + (mu3[0][2] - mu3[0][0]));
+    const C gmy = k3 * (mu3[2][1] - mu3[0][1]) + k12 * ((mu3[2][2] - mu3[0][2]) + (mu3[2][0] - mu3[0][0]));
+    const C rs = C(p.rho_slope);
+    const C grx = rs * gpx, gry = rs * gpy;
+    const C dB = phi - C(p.phiB);
+    const C rho = C(p.rhoB) + dB * rs;
+    const C nu = C(p.nuB) + dB * C(p.nu_slope);
+    const C tau = half + three * nu;
+    const C wg = one / tau, kG = one - half * wg;
+    const C Fx = C(p.gx) - phi * gmx, Fy = C(p.gy) - phi * gmy;
+    const C mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
+    const C my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
+    const C irho = one / rho;
+    const C ux = (mx + half * Fx) * irho, uy = (my + half * Fy) * irho;
+    const C uu = ux * ux + uy * uy;
+    const C snz = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
+    const C s0 = -C(2.0 / 3.0) * uu;  // s_0(u) = w_0 (-u.u / (2 c_s^2))
+    const C C06 = C(CS2 / (1.0 - w_of(0)));
+    const C pr = C06 * (snz + half * (ux * grx + uy * gry) + rho * s0);
 
     // ---- seeds
-    double a[9], c[9];
-    double lS;
+    C a[9], c[9];
+    C lS;
     if (INIT) {
 #pragma unroll
-      for (int i = 0; i < 9; ++i) a[i] = c[i] = 0.0;
-      lS = (double)lam_in[18 * n + kd];
+      for (int i = 0; i < 9; ++i) a[i] = c[i] = C(0);
     } else {
       // P^T: lambda_{f*_j}(x) = lambda'_j(x + c_j) if that link is fluid,
       // else lambda'_opp(j)(x) (the bounce-back image).
 #pragma unroll
       for (int j = 0; j < 9; ++j) {
         int tx = x + cx_of(j), ty = y + cy_of(j);
-        bool wall = (p.bcx && (tx < 0 || tx >= p.nx)) || (p.bcy && (ty < 0 || ty >= p.ny));
+        const bool wall = (p.bcx && (tx < 0 || tx >= p.nx)) || (p.bcy && (ty < 0 || ty >= p.ny));
         long long k;
         int pl;
         if (wall) {
@@ -227,50 +254,51 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
           k = (long long)ty * p.nx + tx;
           pl = j;
         }
-        a[j] = (double)lam_in[pl * n + k];
-        c[j] = (double)lam_in[(9 + pl) * n + k];
+        a[j] = lam_in[pl * n + k];
+        c[j] = lam_in[(9 + pl) * n + k];
       }
-      lS = (double)lam_in[18 * n + kd];  // S_prev(n+1) = S(n), no streaming
     }
+    lS = lam_in[18 * n + kd];  // S_prev(n+1) = S(n): no streaming
 
     // ---- order-parameter collision: f* = f - w_f (f - f^eq) + w b (3/2 S - 1/2 S_prev)
-    const double wf = p.omega_f;
-    double swb = 0.0, lwf = 0.0, qeq = 0.0;
+    const C wf = C(p.omega_f), alpha = C(p.alpha);
+    C swb = C(0), lwf = C(0), qeq = C(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      swb += w_of(i) * src_bracket(i) * a[i];
-      const double feq = i == 0 ? phi - (1.0 - w_of(0)) * p.alpha * mu : w_of(i) * p.alpha * mu;
+      swb += C(w_of(i) * src_bracket(i)) * a[i];
+      const C feq = i == 0 ? phi - C(1.0 - w_of(0)) * alpha * mu : C(w_of(i)) * alpha * mu;
       lwf += a[i] * (feq - f[i]);
-      qeq += (i == 0 ? -(1.0 - w_of(0)) : w_of(i)) * (wf * a[i]);
+      qeq += C(i == 0 ? -(1.0 - w_of(0)) : w_of(i)) * (wf * a[i]);
     }
-    double lphi = wf * a[0];       // d f^eq_0 / d phi = 1
-    const double lmu = p.alpha * qeq;
-    th[0] += mu * qeq;             // d/d alpha
-    th[1] += -(wf * wf) * lwf;     // d/d tau_f through 1/tau_f
-    const double lSt = lS + 1.5 * swb;
-    const double lSp_out = -0.5 * swb;
+    C lphi = wf * a[0];       // d f^eq_0 / d phi = 1
+    const C lmu = alpha * qeq;
+    th[0] += (double)(mu * qeq);          // d/d alpha
+    th[1] += (double)(-(wf * wf) * lwf);  // d/d tau_f through 1/tau_f
+    const C lSt = lS + C(1.5) * swb;
+    const C lSp_out = -half * swb;
 
     // ---- hydrodynamic collision: g* = g - w_g (g - g^eq) + k_G G~
-    double lwg = 0.0, lkG = 0.0, lp = 0.0, lrho = 0.0;
-    double lux = 0.0, luy = 0.0, lFx = 0.0, lFy = 0.0, lgrx = 0.0, lgry = 0.0;
+    C lwg = C(0), lkG = C(0), lp = C(0), lrho = C(0);
+    C lux = C(0), luy = C(0), lFx = C(0), lFy = C(0), lgrx = C(0), lgry = C(0);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-      const double cxi = cx_of(i), cyi = cy_of(i), wi = w_of(i);
-      const double cu = cxi * ux + cyi * uy;
-      const double cF = cxi * Fx + cyi * Fy;
-      const double cr = cxi * grx + cyi * gry;
-      const double si = wi * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu);
-      const double geq = (pr * INV_CS2) * (wi - (i == 0 ? 1.0 : 0.0)) + rho * si;
+      const C cxi = C(cx_of(i)), cyi = C(cy_of(i)), wi = C(w_of(i));
+      const C cu = cxi * ux + cyi * uy;
+      const C cF = cxi * Fx + cyi * Fy;
+      const C cr = cxi * grx + cyi * gry;
+      const C si = wi * (three * cu + C(4.5) * cu * cu - C(1.5) * uu);
+      const C pw = C(INV_CS2 * (w_of(i) - (i == 0 ? 1.0 : 0.0)));
+      const C geq = pr * pw + rho * si;
       lwg += c[i] * (geq - g[i]);
-      const double Gt = 3.0 * wi * (cF + cu * cr);
+      const C Gt = three * wi * (cF + cu * cr);
       lkG += c[i] * Gt;
-      const double lgeq = wg * c[i];
-      lp += lgeq * INV_CS2 * (wi - (i == 0 ? 1.0 : 0.0));
+      const C lgeq = wg * c[i];
+      lp += lgeq * pw;
       lrho += lgeq * si;
-      const double rl = rho * lgeq * wi;
-      lux += rl * (3.0 * cxi + 9.0 * cu * cxi - 3.0 * ux);
-      luy += rl * (3.0 * cyi + 9.0 * cu * cyi - 3.0 * uy);
-      const double kc = kG * c[i] * 3.0 * wi;
+      const C rl = rho * lgeq * wi;
+      lux += rl * (three * cxi + C(9.0) * cu * cxi - three * ux);
+      luy += rl * (three * cyi + C(9.0) * cu * cyi - three * uy);
+      const C kc = kG * c[i] * three * wi;
       lFx += kc * cxi;
       lFy += kc * cyi;
       lux += kc * cr * cxi;
@@ -279,31 +307,31 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
       lgry += kc * cu * cyi;
     }
     // tau_g = 1/2 + 3 nu(phi); w_g = 1/tau_g; k_G = 1 - w_g/2
-    const double lwg_t = lwg - 0.5 * lkG;
-    const double lnu = INV_CS2 * (-(wg * wg) * lwg_t);
-    lphi += lnu * p.nu_slope;
-    const double t = dB / (p.phiA - p.phiB);
-    th[2] += lnu * t;
-    th[3] += lnu * (1.0 - t);
+    const C lwg_t = lwg - half * lkG;
+    const C lnu = three * (-(wg * wg) * lwg_t);
+    lphi += lnu * C(p.nu_slope);
+    const C t = dB * C(1.0 / (p.phiA - p.phiB));
+    th[2] += (double)(lnu * t);
+    th[3] += (double)(lnu * (one - t));
     // S = u . grad phi
     lux += lSt * gpx;
     luy += lSt * gpy;
-    double lgpx = lSt * ux, lgpy = lSt * uy;
+    C lgpx = lSt * ux, lgpy = lSt * uy;
     // p = C06 (snz + u.grad(rho)/2 + rho s_0(u)), s_0 = -(2/3) |u|^2
-    const double lsnz = C06 * lp;
-    lux += C06 * lp * (0.5 * grx - (4.0 / 3.0) * rho * ux);
-    luy += C06 * lp * (0.5 * gry - (4.0 / 3.0) * rho * uy);
-    lgrx += C06 * lp * 0.5 * ux;
-    lgry += C06 * lp * 0.5 * uy;
+    const C lsnz = C06 * lp;
+    lux += C06 * lp * (half * grx - C(4.0 / 3.0) * rho * ux);
+    luy += C06 * lp * (half * gry - C(4.0 / 3.0) * rho * uy);
+    lgrx += C06 * lp * half * ux;
+    lgry += C06 * lp * half * uy;
     lrho += C06 * lp * s0;
     // rho u = m + F/2
-    const double lmx = lux / rho, lmy = luy / rho;
-    lFx += 0.5 * lmx;
-    lFy += 0.5 * lmy;
-    lrho += -(lux * ux + luy * uy) / rho;
+    const C lmx = lux * irho, lmy = luy * irho;
+    lFx += half * lmx;
+    lFy += half * lmy;
+    lrho += -(lux * ux + luy * uy) * irho;
     // F = -phi grad mu + G
     lphi += -(lFx * gmx + lFy * gmy);
-    const double lgmx = -phi * lFx, lgmy = -phi * lFy;
+    const C lgmx = -phi * lFx, lgmy = -phi * lFy;
     // rho(phi) and grad rho = rho_slope grad phi
     lphi += rs * lrho;
     lgpx += rs * lgrx;
@@ -312,76 +340,121 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
     // ---- outputs
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      lam_out[(9 + i) * n + kd] = (T)((1.0 - wg) * c[i] + (double)cx_of(i) * lmx +
-                                      (double)cy_of(i) * lmy + (i ? lsnz : 0.0));
-    lam_out[18 * n + kd] = (T)(INIT ? 0.0 : lSp_out);
-    w.lphi[kd] = (T)lphi;
-    w.lmu[kd] = (T)lmu;
-    w.lgpx[kd] = (T)lgpx;
-    w.lgpy[kd] = (T)lgpy;
-    w.lgmx[kd] = (T)lgmx;
-    w.lgmy[kd] = (T)lgmy;
-    (void)o;
+      lam_out[(9 + i) * n + kd] = (one - wg) * c[i] + C(cx_of(i)) * lmx + C(cy_of(i)) * lmy + (i ? lsnz : C(0));
+    lam_out[18 * n + kd] = INIT ? C(0) : lSp_out;
+    w.lphi[kd] = lphi;
+    w.lmu[kd] = lmu;
+    w.lgpx[kd] = lgpx;
+    w.lgpy[kd] = lgpy;
+    w.lgmx[kd] = lgmx;
+    w.lgmy[kd] = lgmy;
   }
   block_sum_add<4>(th, th_part + (long long)tile * NTH + 2);
 }
 
-// ------------------------------------------------------------------ KA2
-template <typename T>
-__global__ __launch_bounds__(256) void ka_mu(const KP p, const T* __restrict__ dphi, AdjWork<T> w,
-                                              double* __restrict__ th_part, int ntx) {
+// ------------------------------------------------------------- KA2 + KA3
+// One pass: lambda_mu_tot = lambda_mu + G^T lambda_{grad mu} on the tile plus
+// a one-cell ring, staged in LDS, then lambda_phi and lambda_f on the tile.
+// L^T reads lambda_mu_tot at the preimages of the target, which lie at
+// offsets {-c} (and {0} for a mirrored wall link) from it: inside the ring.
+__device__ __forceinline__ int pre_off(int v, int c, int n, int wall, int (&out)[2]) {
+  if (!wall) {
+    out[0] = -c;
+    return 1;
+  }
+  if (c == 0) {
+    out[0] = 0;
+    return 1;
+  }
+  int k = 0;
+  if (c == 1) {
+    if (v - 1 >= 0) out[k++] = -1;
+    if (v == n - 1) out[k++] = 0;
+  } else {
+    if (v + 1 <= n - 1) out[k++] = 1;
+    if (v == 0) out[k++] = 0;
+  }
+  return k;
+}
+
+template <typename T, bool INIT>
+__global__ __launch_bounds__(256) void ka_mu_phi(const KP p, const T* __restrict__ dphi,
+                                                  const T* __restrict__ lam_in, T* __restrict__ lam_out,
+                                                  AdjWork<T> w, double* __restrict__ th_part, int ntx) {
+  using C = T;  // arithmetic in the storage type, as in ka_local
+  constexpr int LW = K2_TX + 2, LH = K2_TY + 2;
+  __shared__ C mt[LH][LW];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x = (tile % ntx) * K2_TX + (threadIdx.x & (K2_TX - 1));
-  const int y = (tile / ntx) * K2_TY + threadIdx.x / K2_TX;
+  const int x0 = (tile % ntx) * K2_TX, y0 = (tile / ntx) * K2_TY;
+  for (int k = threadIdx.x; k < LH * LW; k += blockDim.x) {
+    const int ly = k / LW, lx = k - ly * LW;
+    int gx = x0 + lx - 1, gy = y0 + ly - 1;
+    C v = C(0);
+    const bool outx = gx < 0 || gx >= p.nx, outy = gy < 0 || gy >= p.ny;
+    if (!((outx && p.bcx) || (outy && p.bcy))) {
+      gx = stencil_idx(gx, p.nx, 0);
+      gy = stencil_idx(gy, p.ny, 0);
+      v = w.lmu[(long long)gy * p.nx + gx] + grad_T<C>(p, w.lgmx, w.lgmy, gx, gy);
+    }
+    mt[ly][lx] = v;
+  }
+  __syncthreads();
+  const int tx = threadIdx.x & (K2_TX - 1), ty = threadIdx.x / K2_TX;
+  const int x = x0 + tx, y = y0 + ty;
   double th[2] = {0.0, 0.0};  // kappa, beta
   if (x < p.nx && y < p.ny) {
+    const long long n = (long long)p.nx * p.ny;
     const long long kd = (long long)y * p.nx + x;
-    const double lmt = (double)w.lmu[kd] + grad_T(p, w.lgmx, w.lgmy, x, y);
-    w.lmu_tot[kd] = (T)lmt;
+    const int lx = tx + 1, ly = ty + 1;
+    const C lmt = mt[ly][lx];
+    // L^T lambda_mu_tot from LDS
+    C lt = C(0);
+    if (single_pre(x, p.nx, p.bcx) && single_pre(y, p.ny, p.bcy)) {
+#pragma unroll
+      for (int d = 1; d < 9; ++d) lt += C(2.0 * INV_CS2 * w_of(d)) * mt[ly - cy_of(d)][lx - cx_of(d)];
+    } else {
+#pragma unroll
+      for (int d = 1; d < 9; ++d) {
+        int ox[2], oy[2];
+        const int nxo = pre_off(x, cx_of(d), p.nx, p.bcx, ox);
+        const int nyo = pre_off(y, cy_of(d), p.ny, p.bcy, oy);
+        for (int a = 0; a < nyo; ++a)
+          for (int b = 0; b < nxo; ++b) lt += C(2.0 * INV_CS2 * w_of(d)) * mt[ly + oy[a]][lx + ox[b]];
+      }
+    }
+    lt -= C(2.0 * INV_CS2 * (1.0 - w_of(0))) * lmt;
+    // forward phi around the cell for lap(phi) and psi
     double v[3][3];
     const int xs[3] = {stencil_idx(x - 1, p.nx, p.bcx), x, stencil_idx(x + 1, p.nx, p.bcx)};
     const int ys[3] = {stencil_idx(y - 1, p.ny, p.bcy), y, stencil_idx(y + 1, p.ny, p.bcy)};
+#pragma unroll
     for (int a = 0; a < 3; ++a)
+#pragma unroll
       for (int b = 0; b < 3; ++b) v[a][b] = (double)dphi[(long long)ys[a] * p.pitch + xs[b]] + p.phi_ref;
-    th[0] = -lap_fwd(v) * lmt;           // mu = psi'(phi) - kappa lap(phi)
-    th[1] = dpsi_b(p, v[1][1]) * lmt;
+    const double ph = v[1][1];
+    th[0] = -lap_fwd(v) * (double)lmt;  // mu = psi'(phi) - kappa lap(phi)
+    th[1] = dpsi_b(p, ph) * (double)lmt;
+    const C lphi = w.lphi[kd] + grad_T<C>(p, w.lgpx, w.lgpy, x, y) +
+                   C(p.beta4 * 0.25 * d2psi_b(p, ph)) * lmt - C(p.kappa) * lt;
+    const C k1 = C(1.0 - p.omega_f);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      C a = C(0);
+      if (!INIT) {
+        int qx = x + cx_of(j), qy = y + cy_of(j);
+        const bool wall = (p.bcx && (qx < 0 || qx >= p.nx)) || (p.bcy && (qy < 0 || qy >= p.ny));
+        if (wall) {
+          a = lam_in[opp_of(j) * n + kd];
+        } else {
+          qx = qx < 0 ? qx + p.nx : (qx >= p.nx ? qx - p.nx : qx);
+          qy = qy < 0 ? qy + p.ny : (qy >= p.ny ? qy - p.ny : qy);
+          a = lam_in[j * n + (long long)qy * p.nx + qx];
+        }
+      }
+      lam_out[j * n + kd] = k1 * a + lphi;
+    }
   }
   block_sum_add<2>(th, th_part + (long long)tile * NTH + 0);
-}
-
-// ------------------------------------------------------------------ KA3
-// lambda_f_i = (1 - w_f) lambda_{f*_i} + lambda_phi.  INIT: lambda_{f*} = 0.
-template <typename T, bool INIT>
-__global__ __launch_bounds__(256) void ka_phi(const KP p, const T* __restrict__ dphi,
-                                               const T* __restrict__ lam_in, T* __restrict__ lam_out,
-                                               AdjWork<T> w, int ntx) {
-  const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x = (tile % ntx) * K2_TX + (threadIdx.x & (K2_TX - 1));
-  const int y = (tile / ntx) * K2_TY + threadIdx.x / K2_TX;
-  if (x >= p.nx || y >= p.ny) return;
-  const long long n = (long long)p.nx * p.ny;
-  const long long kd = (long long)y * p.nx + x;
-  const double ph = (double)dphi[(long long)y * p.pitch + x] + p.phi_ref;
-  const double lmt = (double)w.lmu_tot[kd];
-  const double lphi = (double)w.lphi[kd] + grad_T(p, w.lgpx, w.lgpy, x, y) +
-                      p.beta4 * 0.25 * d2psi_b(p, ph) * lmt - p.kappa * lap_T(p, w.lmu_tot, x, y);
-  const double k1 = 1.0 - p.omega_f;
-#pragma unroll
-  for (int j = 0; j < 9; ++j) {
-    double a = 0.0;
-    if (!INIT) {
-      int tx = x + cx_of(j), ty = y + cy_of(j);
-      bool wall = (p.bcx && (tx < 0 || tx >= p.nx)) || (p.bcy && (ty < 0 || ty >= p.ny));
-      if (wall) {
-        a = (double)lam_in[opp_of(j) * n + kd];
-      } else {
-        tx = tx < 0 ? tx + p.nx : (tx >= p.nx ? tx - p.nx : tx);
-        ty = ty < 0 ? ty + p.ny : (ty >= p.ny ? ty - p.ny : ty);
-        a = (double)lam_in[j * n + (long long)ty * p.nx + tx];
-      }
-    }
-    lam_out[j * n + kd] = (T)(k1 * a + lphi);
-  }
 }
 
 // ---------------------------------------------------- initialisation adjoint

@@ -334,34 +334,74 @@ AdjWork<T> adj_work(lbm_ctx* c) {
   return AdjWork<T>{q[0], q[1], q[2], q[3], q[4], q[5], q[6]};
 }
 
+// Snapshot layout: [NB pop planes][S_prev][dphi][mu], plane stride as in the
+// state.  The phi/mu planes are scratch that lbm_step_into fills for its
+// source, so the adjoint of that state need not recompute them.
 template <typename T>
-const T* snap_S(const lbm_ctx* c, const T* snap) {
-  return snap + (size_t)Store<T>::NB * c->kp.ps;
+T* snap_S(const lbm_ctx* c, const T* snap) {
+  return const_cast<T*>(snap) + (size_t)Store<T>::NB * c->kp.ps;
+}
+template <typename T>
+T* snap_dphi(const lbm_ctx* c, const T* snap) {
+  return snap_S(c, snap) + c->kp.ps;
+}
+template <typename T>
+T* snap_mu(const lbm_ctx* c, const T* snap) {
+  return snap_S(c, snap) + 2 * c->kp.ps;
 }
 
 template <typename T>
-int step_into_impl(lbm_ctx* c, const T* src, T* dst) {
-  int r = launch_phi_mu<T>(c, src);
-  if (r) return r;
-  return launch_collide<T, M_STEP>(c, MomOut{}, src, dst, snap_S(c, src), const_cast<T*>(snap_S(c, dst)));
+int step_into_impl(lbm_ctx* c, T* src, T* dst) {
+  hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, src,
+                     nullptr, snap_dphi(c, src), snap_mu(c, src), c->ntx1);
+  LAUNCHCHK(c);
+  hipLaunchKernelGGL((k_collide<T, M_STEP>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream, c->kp, src,
+                     dst, snap_S(c, src), snap_S(c, dst), snap_dphi(c, src), snap_mu(c, src), MomOut{},
+                     c->partials, c->ntx2);
+  LAUNCHCHK(c);
+  return LBM_OK;
 }
 
 template <typename T>
-int adjoint_step_impl(lbm_ctx* c, const T* state, const T* lam_in, T* lam_out) {
-  int r = launch_phi_mu<T>(c, state);
-  if (r) return r;
+int adjoint_step_impl(lbm_ctx* c, T* state, const T* lam_in, T* lam_out, bool have_phi_mu) {
+  T* dphi = snap_dphi(c, state);
+  T* mu = snap_mu(c, state);
+  if (!have_phi_mu) {
+    hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, state,
+                       nullptr, dphi, mu, c->ntx1);
+    LAUNCHCHK(c);
+  }
   const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
   const AdjWork<T> w = adj_work<T>(c);
   hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state,
-                     snap_S(c, state), dphi_plane<T>(c), mu_plane<T>(c), lam_in, lam_out, w, c->th_part,
-                     c->ntx2);
+                     snap_S(c, state), dphi, mu, lam_in, lam_out, w, c->th_part, c->ntx2);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL(ka_mu<T>, dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), w, c->th_part,
-                     c->ntx2);
+  hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi, lam_in, lam_out,
+                     w, c->th_part, c->ntx2);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL((ka_phi<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c),
-                     lam_in, lam_out, w, c->ntx2);
-  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+// Recompute the states of one checkpoint segment (snaps[0] holds s_k, the
+// others receive s_{k+1}..s_{k+L-1}) and run the L adjoint steps in reverse,
+// ping-ponging lambda between lam and tmp.  Returns the buffer holding
+// dL/ds_k in *which (0: lam, 1: tmp).
+template <typename T>
+int adjoint_segment_impl(lbm_ctx* c, T* const* snaps, int L, T* lam, T* tmp, int* which) {
+  for (int k = 1; k < L; ++k) {
+    int r = step_into_impl<T>(c, snaps[k - 1], snaps[k]);
+    if (r) return r;
+  }
+  T* a = lam;
+  T* b = tmp;
+  for (int k = L - 1; k >= 0; --k) {
+    int r = adjoint_step_impl<T>(c, snaps[k], a, b, k < L - 1);
+    if (r) return r;
+    T* t = a;
+    a = b;
+    b = t;
+  }
+  *which = a == lam ? 0 : 1;
   return LBM_OK;
 }
 
@@ -376,11 +416,8 @@ int adjoint_init_impl(lbm_ctx* c, const T* state, const double* phi0, const T* l
                      snap_S(c, state), dphi_plane<T>(c), mu_plane<T>(c), lam0, scratch, w, c->th_part,
                      c->ntx2);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL(ka_mu<T>, dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), w, c->th_part,
-                     c->ntx2);
-  LAUNCHCHK(c);
-  hipLaunchKernelGGL((ka_phi<T, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), lam0,
-                     scratch, w, c->ntx2);
+  hipLaunchKernelGGL((ka_mu_phi<T, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), lam0,
+                     scratch, w, c->th_part, c->ntx2);
   LAUNCHCHK(c);
   // mu0 = mu(phi0) into the mu plane
   hipLaunchKernelGGL((k_phi_mu<T, true>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, nullptr,
@@ -397,7 +434,7 @@ int adjoint_init_impl(lbm_ctx* c, const T* state, const double* phi0, const T* l
 
 size_t snapshot_bytes(const lbm_ctx* c) {
   const size_t nb = c->prec == 64 ? Store<double>::NB : Store<float>::NB;
-  return (nb + 1) * (size_t)c->kp.ps * c->esz;
+  return (nb + 3) * (size_t)c->kp.ps * c->esz;
 }
 
 }  // namespace
@@ -593,22 +630,34 @@ int lbm_adjoint_attach(lbm_ctx* c, void* adj_workspace) {
   return LBM_OK;
 }
 
-int lbm_step_into(lbm_ctx* c, const void* src, void* dst) {
+int lbm_step_into(lbm_ctx* c, void* src, void* dst) {
   if (!c || !src || !dst || src == dst) return LBM_EINVAL;
   if (((uintptr_t)src & 255) || ((uintptr_t)dst & 255)) return LBM_EINVAL;
-  return c->prec == 64 ? step_into_impl<double>(c, static_cast<const double*>(src), static_cast<double*>(dst))
-                       : step_into_impl<float>(c, static_cast<const float*>(src), static_cast<float*>(dst));
+  return c->prec == 64 ? step_into_impl<double>(c, static_cast<double*>(src), static_cast<double*>(dst))
+                       : step_into_impl<float>(c, static_cast<float*>(src), static_cast<float*>(dst));
 }
 
-int lbm_adjoint_step(lbm_ctx* c, const void* state, const void* lam_in, void* lam_out) {
+int lbm_adjoint_step(lbm_ctx* c, void* state, const void* lam_in, void* lam_out, int flags) {
   if (!c || !state || !lam_in || !lam_out || lam_in == lam_out) return LBM_EINVAL;
-  if ((uintptr_t)state & 255) return LBM_EINVAL;
+  if (((uintptr_t)state & 255) || (flags & ~LBM_SNAPSHOT_HAS_PHI_MU)) return LBM_EINVAL;
   if (!c->adj) return LBM_ESTATE;
-  return c->prec == 64
-             ? adjoint_step_impl<double>(c, static_cast<const double*>(state), static_cast<const double*>(lam_in),
-                                         static_cast<double*>(lam_out))
-             : adjoint_step_impl<float>(c, static_cast<const float*>(state), static_cast<const float*>(lam_in),
-                                        static_cast<float*>(lam_out));
+  const bool have = (flags & LBM_SNAPSHOT_HAS_PHI_MU) != 0;
+  return c->prec == 64 ? adjoint_step_impl<double>(c, static_cast<double*>(state),
+                                                   static_cast<const double*>(lam_in),
+                                                   static_cast<double*>(lam_out), have)
+                       : adjoint_step_impl<float>(c, static_cast<float*>(state), static_cast<const float*>(lam_in),
+                                                  static_cast<float*>(lam_out), have);
+}
+
+int lbm_adjoint_segment(lbm_ctx* c, void* const* snaps, int L, void* lam, void* tmp, int* which) {
+  if (!c || !snaps || L < 1 || !lam || !tmp || !which || lam == tmp) return LBM_EINVAL;
+  for (int k = 0; k < L; ++k)
+    if (!snaps[k] || ((uintptr_t)snaps[k] & 255)) return LBM_EINVAL;
+  if (!c->adj) return LBM_ESTATE;
+  return c->prec == 64 ? adjoint_segment_impl<double>(c, reinterpret_cast<double* const*>(snaps), L,
+                                                      static_cast<double*>(lam), static_cast<double*>(tmp), which)
+                       : adjoint_segment_impl<float>(c, reinterpret_cast<float* const*>(snaps), L,
+                                                     static_cast<float*>(lam), static_cast<float*>(tmp), which);
 }
 
 int lbm_adjoint_init(lbm_ctx* c, const void* state, const double* phi0, const void* lam0, void* scratch,

@@ -192,9 +192,21 @@ class Sim:
         """Zeroed adjoint of a state: 19 planes (f_0..f_8, g_0..g_8, S_prev)."""
         return torch.zeros((19,) + self.shape, dtype=_storage_dtype(self.p.precision), device=self.device)
 
-    def adjoint_step(self, state: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor) -> None:
-        check(self.L.lbm_adjoint_step(self.ctx, _ptr(state), _ptr(lam_in), _ptr(lam_out)),
+    def adjoint_step(self, state: torch.Tensor, lam_in: torch.Tensor, lam_out: torch.Tensor,
+                     have_phi_mu: bool = False) -> None:
+        flags = _lib.SNAPSHOT_HAS_PHI_MU if have_phi_mu else 0
+        check(self.L.lbm_adjoint_step(self.ctx, _ptr(state), _ptr(lam_in), _ptr(lam_out), flags),
               "lbm_adjoint_step", self.ctx)
+
+    def adjoint_segment(self, snaps, lam: torch.Tensor, tmp: torch.Tensor) -> int:
+        """Recompute a checkpoint segment and run its adjoint steps natively.
+
+        Returns 0 if dL/d(first state) is in ``lam``, 1 if in ``tmp``."""
+        arr = (ctypes.c_void_p * len(snaps))(*[t.data_ptr() for t in snaps])
+        which = ctypes.c_int()
+        check(self.L.lbm_adjoint_segment(self.ctx, arr, len(snaps), _ptr(lam), _ptr(tmp),
+                                         ctypes.byref(which)), "lbm_adjoint_segment", self.ctx)
+        return which.value
 
     def adjoint_init(self, state0: torch.Tensor, phi0: torch.Tensor, lam0: torch.Tensor,
                      scratch: torch.Tensor) -> torch.Tensor:
