@@ -25,13 +25,15 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline, FP32 vs FP64 step; adjoint/forward step cost ratio"
 HBM_PEAK_GBPS = 8000.0
-# Algorithmic HBM bytes per lattice update of each kernel (per cell):
-#   collide-stream: 18 populations read + 18 written (FP32: 19, the rest
-#                   population of f as hi + lo), phi and mu read once,
-#                   previous source read and new source written;
-#   phi/mu pass:    9 populations read (FP32: 10), phi and mu written.
-COLLIDE_BYTES = {32: (19 + 19 + 2 + 2) * 4, 64: (18 + 18 + 2 + 2) * 8}
-PHIMU_BYTES = {32: (10 + 2) * 4, 64: (9 + 2) * 8}
+# Algorithmic HBM bytes per lattice update (per cell) of the fused step
+# kernel, the only kernel of a step: every population plane read once and
+# written once (18 in FP64; 19 in FP32, where the rest population of f is a
+# hi + lo pair), the previous-step source read and the new one written.
+# phi and mu stay on chip.
+STEP_BYTES = {32: (19 + 19 + 1 + 1) * 4, 64: (18 + 18 + 1 + 1) * 8}
+# The two-kernel path also writes phi and mu and reads them back, and reads
+# the f planes twice: +(2 + 2 + 10) * 4 B in FP32, +(2 + 2 + 9) * 8 B in FP64.
+TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (2 + 2 + 10) * 4, 64: STEP_BYTES[64] + (2 + 2 + 9) * 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_many_drops_16384.json")
 
 
@@ -63,19 +65,20 @@ def measured_traffic(prec: int):
     return rec.get("bytes_per_launch")
 
 
-def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl):
+def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl, kernel_path: int = 0):
     import torch
     from paper_2311_10827_amd.sim import Sim, make_params
 
-    p = make_params(wl, precision=prec)
+    p = make_params(wl, precision=prec, kernel_path=kernel_path)
     sim = Sim(p, phi0_dev, device=phi0_dev.device)
     stream = sim.stream
     ncell = wl.nx * wl.ny
-    log(f"[bench] fp{prec}: warmup {warmup}")
+    tag = f"fp{prec}{'' if kernel_path == 0 else ' two-kernel'}"
+    log(f"[bench] {tag}: warmup {warmup}")
     sim.step(warmup)
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    log(f"[bench] fp{prec}: timing {steps} steps")
+    log(f"[bench] {tag}: timing {steps} steps")
     t0 = time.perf_counter()
     e0.record(stream)
     sim.step(steps)
@@ -83,11 +86,11 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = e0.elapsed_time(e1)
-    # per-kernel durations with HIP events recorded by the library on its stream
-    log(f"[bench] fp{prec}: per-kernel timing over {kernel_steps} steps")
+    # kernel durations with HIP events the library records on its own stream
+    log(f"[bench] {tag}: per-kernel timing over {kernel_steps} steps")
     sim.timing(True)
     sim.step(kernel_steps)
-    k1, k2, n = sim.kernel_times()
+    kms, n = sim.kernel_times()
     sim.timing(False)
     m = sim.moments()
     d = m["diag"]
@@ -95,24 +98,22 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl)
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    avg_k1, avg_k2 = k1 / n, k2 / n
-    ach = COLLIDE_BYTES[prec] * ncell / (avg_k2 * 1e-3) / 1e9
-    traffic = measured_traffic(prec)
+    avg = kms / n
+    alg = STEP_BYTES[prec] if kernel_path == 0 else TWO_KERNEL_BYTES[prec]
+    ach = alg * ncell / (avg * 1e-3) / 1e9
     return {
         "mlups": ncell * steps / (ms * 1e-3) / 1e6,
         "ms_per_step": ms / steps,
         "wall_s": wall,
-        "kernels_ms": {"phi_mu": avg_k1, "collide_stream": avg_k2},
+        "kernel_ms": avg,
         "roofline": {
             "bound": "hbm",
             "achieved": round(ach, 1),
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBPS, 4),
-            "traffic": traffic,
+            "traffic": measured_traffic(prec) if kernel_path == 0 else None,
         },
-        "phi_mu_GBps": round(PHIMU_BYTES[prec] * ncell / (avg_k1 * 1e-3) / 1e9, 1),
-        "step_GBps_alg": round((COLLIDE_BYTES[prec] + PHIMU_BYTES[prec]) * ncell / (ms / steps * 1e-3) / 1e9, 1),
         "diag_after": {k: d[k] for k in ("sum_phi", "max_u", "min_rho", "n_nonfinite", "step")},
     }
 
@@ -229,6 +230,7 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-two-kernel", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-K", type=int, default=100)
     args = ap.parse_args()
@@ -251,6 +253,9 @@ def main():
     r64 = None
     if not args.no_fp64:
         r64 = run_gpu(phi0_dev, 64, args.fp64_steps or args.steps, args.warmup, args.kernel_steps, wl)
+    r2k = None
+    if not args.no_two_kernel:
+        r2k = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, kernel_path=1)
     del phi0_dev
     torch.cuda.empty_cache()
     copy_gbps = None if args.no_copy else stream_copy_probe(dev)
@@ -278,14 +283,17 @@ def main():
         },
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
-        "kernels_ms": r32["kernels_ms"],
-        "phi_mu_GBps": r32["phi_mu_GBps"],
-        "step_GBps_alg": r32["step_GBps_alg"],
+        "kernel_ms": round(r32["kernel_ms"], 4),
+        "algorithmic_bytes_per_cell": STEP_BYTES[32],
         "stream_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
         "fp64": None if r64 is None else {
             "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 4),
-            "roofline": r64["roofline"], "kernels_ms": r64["kernels_ms"],
-            "phi_mu_GBps": r64["phi_mu_GBps"], "step_GBps_alg": r64["step_GBps_alg"],
+            "kernel_ms": round(r64["kernel_ms"], 4), "algorithmic_bytes_per_cell": STEP_BYTES[64],
+            "roofline": r64["roofline"],
+        },
+        "two_kernel_fp32": None if r2k is None else {
+            "value": round(r2k["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r2k["ms_per_step"], 4),
+            "algorithmic_bytes_per_cell": TWO_KERNEL_BYTES[32], "roofline": r2k["roofline"],
         },
         "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],

@@ -77,6 +77,9 @@ enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
  *                      from the rest equilibrium; diagnostics stay FP64.
  *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
  *                  diagnostic pass every k steps (see lbm_step).
+ *   kernel_path    0: one fused kernel per step (phi and mu kept on chip);
+ *                  1: the phi/mu pass and the collide-stream pass as two
+ *                  kernels.  Both give the same results bit for bit.
  */
 typedef struct lbm_params {
   int32_t nx, ny;
@@ -91,7 +94,7 @@ typedef struct lbm_params {
   double M, alpha;
   double gx, gy;
   int32_t diag_every;
-  int32_t reserved;
+  int32_t kernel_path;
 } lbm_params;
 
 /* Derived constants (lattice units). */
@@ -151,11 +154,11 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace,
              const double* phi0, const double* ux0, const double* uy0, void* stream);
 
 /*
- * Advance n >= 0 time steps.  One step is two kernels: the phi/mu stencil
- * pass (phi = sum_i f_i, Sec. 2.3.1, eq. order-parameter; mu by eq.
- * chemical_potencial with the isotropic Laplacian of Sec. 2.3.2, eq. Laplace)
- * and the fused collide-and-pull-stream pass (Sec. 2.3.1, eq. BGK;
- * Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi and the u, p recovery).
+ * Advance n >= 0 time steps.  A step computes phi = sum_i f_i (Sec. 2.3.1,
+ * eq. order-parameter) and mu (eq. chemical_potencial with the isotropic
+ * Laplacian of Sec. 2.3.2, eq. Laplace), then collides and pull-streams both
+ * populations (Sec. 2.3.1, eq. BGK; Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi
+ * and the u, p recovery), in one kernel or two (kernel_path).
  * Asynchronous.  With diag_every = k > 0 every k-th step also reduces the
  * diagnostics of its pre-collision state; a pass that found a non-finite
  * value or rho <= 0 makes a later lbm_step (or lbm_last_diag) return
@@ -196,12 +199,12 @@ int lbm_get_state(lbm_ctx* ctx, int32_t x0, int32_t y0, int32_t w, int32_t h, do
 int lbm_set_state(lbm_ctx* ctx, const double* f, const double* g, const double* Sp,
                   int64_t step);
 
-/* Per-kernel timing with HIP events recorded on the context's stream.
- * lbm_timing(ctx, 1) starts recording (clearing earlier records), 0 stops.
- * lbm_kernel_times synchronises and returns the summed milliseconds of the
- * phi/mu pass and of the collide-stream pass and the number of steps timed. */
+/* Step timing with HIP events recorded around each step's kernels on the
+ * context's stream.  lbm_timing(ctx, 1) starts recording (clearing earlier
+ * records), 0 stops.  lbm_kernel_times synchronises and returns the summed
+ * milliseconds of the timed steps and their number. */
 int lbm_timing(lbm_ctx* ctx, int enable);
-int lbm_kernel_times(lbm_ctx* ctx, double* ms_phi_mu, double* ms_collide, int64_t* steps);
+int lbm_kernel_times(lbm_ctx* ctx, double* ms_step, int64_t* steps);
 
 /* Bandwidth probe: copy `bytes` (a multiple of 16) from src to dst on
  * `stream` with a plain streaming kernel (device pointers, 16-byte aligned,

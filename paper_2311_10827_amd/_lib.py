@@ -38,7 +38,7 @@ class LbmParams(ctypes.Structure):
         ("sigma", ctypes.c_double), ("W", ctypes.c_double),
         ("M", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
-        ("diag_every", ctypes.c_int32), ("reserved", ctypes.c_int32),
+        ("diag_every", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
     ]
 
 
@@ -103,8 +103,7 @@ def load() -> ctypes.CDLL:
     L.lbm_set_state.restype = ctypes.c_int
     L.lbm_timing.argtypes = [vp, ctypes.c_int]
     L.lbm_timing.restype = ctypes.c_int
-    L.lbm_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double),
-                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
+    L.lbm_kernel_times.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(i64)]
     L.lbm_kernel_times.restype = ctypes.c_int
     L.lbm_stream_copy.argtypes = [vp, vp, ctypes.c_size_t, vp]
     L.lbm_stream_copy.restype = ctypes.c_int

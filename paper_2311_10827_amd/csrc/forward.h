@@ -60,6 +60,42 @@ __device__ __forceinline__ double s_f64(int i, double ux, double uy, double uu) 
   return w_of(i) * ((cu * INV_CS2 + ((0.5 * cu) * cu) * INV_CS2 * INV_CS2) - (0.5 * uu) * INV_CS2);
 }
 
+// phi - phi_ref of a cell from its gathered f (Sec. 2.3.1, eq. order-parameter):
+// FP64 sums f_0..f_8 in index order; FP32 adds the small sum to hi + lo.
+template <typename T>
+__device__ __forceinline__ T phi_sum(const Pops<T>& q) {
+  if constexpr (std::is_same<T, double>::value) {
+    double a = q.f[0];
+#pragma unroll
+    for (int i = 1; i < 9; ++i) a = a + q.f[i];
+    return a;
+  } else {
+    const float s8 = ((q.f[1] + q.f[2]) + (q.f[3] + q.f[4])) + ((q.f[5] + q.f[6]) + (q.f[7] + q.f[8]));
+    return q.f[0] + (q.lo + s8);
+  }
+}
+
+// mu = 4 beta (phi - phi_A)(phi - phi_B)(phi - phi_m) - kappa lap(phi)
+// (Sec. 2.1, eq. chemical_potencial; Sec. 2.3.2, eq. Laplace) from the 3x3
+// values of phi - phi_ref, v[dy+1][dx+1].  FP64 in plain-definition order;
+// FP32 in difference form.
+template <typename C>
+__device__ __forceinline__ C mu_cell(const KP& p, const C (&v)[3][3]) {
+  const C c = v[1][1];
+  if constexpr (std::is_same<C, double>::value) {
+    const double ph = c + p.phi_ref;
+    const double lap = lap_f64(v);
+    return (((p.beta4 * (ph - p.phiA)) * (ph - p.phiB)) * (ph - p.phim)) - p.kappa * lap;
+  } else {
+    const C axis = ((v[1][2] - c) + (v[1][0] - c)) + ((v[2][1] - c) + (v[0][1] - c));
+    const C diag = ((v[2][2] - c) + (v[2][0] - c)) + ((v[0][2] - c) + (v[0][0] - c));
+    const C lap = (C)(2.0 / 3.0) * axis + (C)(1.0 / 6.0) * diag;
+    const C dA = c + (C)(p.phi_ref - p.phiA), dB = c + (C)(p.phi_ref - p.phiB);
+    const C dm = c + (C)(p.phi_ref - p.phim);
+    return ((C)p.beta4 * (dA * dB)) * dm - (C)p.kappa * lap;
+  }
+}
+
 // ----------------------------------------------------------- K1: phi and mu
 // phi = sum_i f_i (Sec. 2.3.1, eq. order-parameter) on a tile plus a one-cell
 // ring, staged in LDS; then mu = 4 beta (phi - phi_A)(phi - phi_B)(phi - phi_m)
@@ -88,15 +124,7 @@ __global__ __launch_bounds__(256) void k_phi_mu(const KP p, const T* __restrict_
     } else {
       Pops<T> q;
       gather<false>(B, p, gx, gy, q);
-      if (std::is_same<T, double>::value) {
-        C a = q.f[0];  // sum over i in index order
-#pragma unroll
-        for (int i = 1; i < 9; ++i) a = a + q.f[i];
-        v = a;
-      } else {
-        const C s8 = ((q.f[1] + q.f[2]) + (q.f[3] + q.f[4])) + ((q.f[5] + q.f[6]) + (q.f[7] + q.f[8]));
-        v = q.f[0] + ((C)q.lo + s8);
-      }
+      v = (C)phi_sum<T>(q);
     }
     s[k] = v;
   }
@@ -108,26 +136,10 @@ __global__ __launch_bounds__(256) void k_phi_mu(const KP p, const T* __restrict_
     const C* r0 = s + ly * LW + lx;  // row y-1 starting at column x-1
     const C* r1 = r0 + LW;
     const C* r2 = r1 + LW;
-    C mu;
-    const C c = r1[1];
-    if (std::is_same<C, double>::value) {
-      const double v[3][3] = {{(double)r0[0], (double)r0[1], (double)r0[2]},
-                              {(double)r1[0], (double)r1[1], (double)r1[2]},
-                              {(double)r2[0], (double)r2[1], (double)r2[2]}};
-      const double ph = (double)c + p.phi_ref;
-      const double lap = lap_f64(v);
-      mu = (C)((((p.beta4 * (ph - p.phiA)) * (ph - p.phiB)) * (ph - p.phim)) - p.kappa * lap);
-    } else {
-      const C axis = ((r1[2] - c) + (r1[0] - c)) + ((r2[1] - c) + (r0[1] - c));
-      const C diag = ((r2[2] - c) + (r2[0] - c)) + ((r0[2] - c) + (r0[0] - c));
-      const C lap = (C)(2.0 / 3.0) * axis + (C)(1.0 / 6.0) * diag;
-      const C dA = c + (C)(p.phi_ref - p.phiA), dB = c + (C)(p.phi_ref - p.phiB);
-      const C dm = c + (C)(p.phi_ref - p.phim);
-      mu = ((C)p.beta4 * (dA * dB)) * dm - (C)p.kappa * lap;
-    }
+    const C v[3][3] = {{r0[0], r0[1], r0[2]}, {r1[0], r1[1], r1[2]}, {r2[0], r2[1], r2[2]}};
     const long long o = (long long)y * p.pitch + x;
-    dphi_out[o] = (T)c;
-    mu_out[o] = (T)mu;
+    dphi_out[o] = (T)v[1][1];
+    mu_out[o] = (T)mu_cell<C>(p, v);
   }
 }
 
@@ -380,6 +392,133 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
 // block then reduces those.  The assignment of partials to lanes depends
 // only on n, so the result is bitwise reproducible.
 constexpr int RED_BLOCKS = 1024;
+// ------------------------------------------- fused step: phi, mu, collide
+// One workgroup owns a strip of FS_W columns and FS_H rows and marches up
+// it.  Per row y it gathers phi of row y+2 (5-row ring in LDS, FS_W + 4
+// columns), computes mu of row y+1 (3-row ring, FS_W + 2 columns) and then
+// collides row y with the same arithmetic as k_collide, reading the 3x3 phi
+// and mu from LDS.  phi and mu never go to HBM unless WRITE_PHIMU asks for
+// them (the adjoint's recompute keeps them).  Same results as k_phi_mu +
+// k_collide, bit for bit.
+//
+// Ghosts: ring entries outside the grid hold phi of the wrapped or mirrored
+// cell; a mu entry just outside a wall holds mu of the adjacent cell (its
+// stencil is shifted by one), which is what the two-kernel path reads
+// through stencil_idx.
+constexpr int FS_W = 256, FS_H = 64;
+
+__device__ __forceinline__ int mod_pos(int a, int m) {
+  const int r = a % m;
+  return r < 0 ? r + m : r;
+}
+
+template <typename T, int MODE, bool WRITE_PHIMU>
+__global__ __launch_bounds__(FS_W) void k_step_fused(const KP p, const T* Bin, T* Bout, const T* Spin,
+                                                      T* Spout, T* __restrict__ dphi_out,
+                                                      T* __restrict__ mu_out, double* __restrict__ partials,
+                                                      int ntx) {
+  constexpr bool DIAG = MODE == M_STEP_DIAG;
+  __shared__ T phr[5][FS_W + 4];  // column x0 - 2 + k
+  __shared__ T mur[3][FS_W + 2];  // column x0 - 1 + k
+  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  const int x0 = (blk % ntx) * FS_W, y0 = (blk / ntx) * FS_H;
+  const int y1 = y0 + FS_H < p.ny ? y0 + FS_H : p.ny;
+  const int t = threadIdx.x;
+
+  auto phi_row = [&](int yu) {
+    const int gy = stencil_idx(yu, p.ny, p.bcy);
+    T* row = phr[mod_pos(yu, 5)];
+    for (int k = t; k < FS_W + 4; k += FS_W) {
+      const int gx = stencil_idx(x0 - 2 + k, p.nx, p.bcx);
+      Pops<T> q;
+      gather<false>(Bin, p, gx, gy, q);
+      const T v = phi_sum<T>(q);
+      row[k] = v;
+      if (WRITE_PHIMU && yu >= y0 && yu < y1 && k >= 2 && k < FS_W + 2 && x0 - 2 + k < p.nx)
+        dphi_out[(long long)yu * p.pitch + (x0 - 2 + k)] = v;
+    }
+  };
+  auto mu_row = [&](int yu) {
+    // rows used by the stencil: shifted inward for a ghost row beyond a wall
+    const int sy = p.bcy ? (yu < 0 ? 1 : (yu >= p.ny ? -1 : 0)) : 0;
+    const T* r0 = phr[mod_pos(yu + sy - 1, 5)];
+    const T* r1 = phr[mod_pos(yu + sy, 5)];
+    const T* r2 = phr[mod_pos(yu + sy + 1, 5)];
+    T* out = mur[mod_pos(yu, 3)];
+    for (int k = t; k < FS_W + 2; k += FS_W) {
+      const int xu = x0 - 1 + k;
+      const int sx = p.bcx ? (xu < 0 ? 1 : (xu >= p.nx ? -1 : 0)) : 0;
+      const int c = k + 1 + sx;  // phi ring index of the stencil centre
+      const T v[3][3] = {{r0[c - 1], r0[c], r0[c + 1]}, {r1[c - 1], r1[c], r1[c + 1]},
+                         {r2[c - 1], r2[c], r2[c + 1]}};
+      const T m = mu_cell<T>(p, v);
+      out[k] = m;
+      if (WRITE_PHIMU && yu >= y0 && yu < y1 && k >= 1 && k <= FS_W && xu < p.nx)
+        mu_out[(long long)yu * p.pitch + xu] = m;
+    }
+  };
+
+  Diag dg;
+  if (DIAG) diag_identity(dg);
+  for (int r = y0 - 2; r <= y0 + 1; ++r) phi_row(r);
+  __syncthreads();
+  mu_row(y0 - 1);
+  mu_row(y0);
+  const int x = x0 + t;
+  for (int y = y0; y < y1; ++y) {
+    phi_row(y + 2);
+    __syncthreads();
+    mu_row(y + 1);
+    __syncthreads();
+    if (x < p.nx) {
+      const long long o = (long long)y * p.pitch + x;
+      Pops<T> q;
+      gather<true>(Bin, p, x, y, q);
+      Nbhd<T> nb;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) {
+        const T* pr = phr[mod_pos(y - 1 + a, 5)];
+        const T* mr = mur[mod_pos(y - 1 + a, 3)];
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+          nb.ph[a][b] = pr[t + 1 + b];
+          nb.mu[a][b] = mr[t + b];
+        }
+      }
+      const T Sp = Spin[o];
+      T fo[9], go[9];
+      T lo = 0;
+      CellOut c;
+      if constexpr (std::is_same<T, double>::value)
+        cell_f64<true>(p, q, nb, Sp, fo, go, c);
+      else
+        cell_f32<true>(p, q, nb, Sp, fo, lo, go, c);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) {
+        Bout[i * p.ps + o] = fo[i];
+        Bout[(9 + i) * p.ps + o] = go[i];
+      }
+      if constexpr (std::is_same<T, float>::value) Bout[LO_PLANE * p.ps + o] = lo;
+      Spout[o] = (T)c.S;
+      if (DIAG) {
+        const bool fin = isfinite(c.phi) && isfinite(c.mu) && isfinite(c.ux) && isfinite(c.uy) &&
+                         isfinite(c.p);
+        Diag e;
+        e.v[0] = c.phi;
+        e.v[1] = 1.5 * c.S - 0.5 * c.Sp;
+        e.v[2] = 0.5 * c.rho * (c.ux * c.ux + c.uy * c.uy);
+        e.v[3] = sqrt(c.ux * c.ux + c.uy * c.uy);
+        e.v[4] = e.v[5] = c.rho;
+        e.v[6] = e.v[7] = c.mu;
+        e.v[8] = e.v[9] = c.phi;
+        e.v[10] = fin ? 0.0 : 1.0;
+        for (int k = 0; k < NQ; ++k) dg.v[k] = diag_op(k, dg.v[k], e.v[k]);
+      }
+    }
+  }
+  if (DIAG) block_reduce_write(dg, partials + (long long)blk * NQ);
+}
+
 __global__ __launch_bounds__(256) void k_reduce_diag(const double* __restrict__ partials, long long n,
                                                       long long chunk, double* __restrict__ out) {
   Diag d;

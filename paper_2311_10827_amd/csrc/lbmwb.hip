@@ -35,6 +35,8 @@ struct lbm_ctx {
   int cur;
   int64_t step;
   int ntx1, nty1, ntx2, nty2;
+  int ntxf, ntyf;       // strips of the fused step kernel
+  bool fused;           // lbm_step runs the fused kernel (kernel_path 0)
   double* partials;
   double* red_mid;      // [RED_BLOCKS][NQ]: first-level reduction results
   double* diag_dev;     // [2][NQ]: fused step diagnostics, moments diagnostics
@@ -62,6 +64,7 @@ int validate(const lbm_params* p, lbm_derived* d) {
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return LBM_EINVAL;
   if (p->precision != 32 && p->precision != 64) return LBM_EINVAL;
   if (p->diag_every < 0) return LBM_EINVAL;
+  if (p->kernel_path != 0 && p->kernel_path != 1) return LBM_EINVAL;
   const size_t pitch = round_up((size_t)p->nx, 64);
   if (pitch * (size_t)p->ny > (size_t)INT32_MAX) return LBM_EINVAL;
   const double dphi = p->phi_A - p->phi_B;
@@ -101,6 +104,8 @@ struct Layout {
   size_t pitch, ps, esz, nb;
   size_t state_bytes, ws_bytes;
   int ntx1, nty1, ntx2, nty2;
+  int ntxf, ntyf;       // strips of the fused step kernel
+  bool fused;           // lbm_step runs the fused kernel (kernel_path 0)
 };
 
 constexpr int ADJ_PLANES = 7;
@@ -188,8 +193,15 @@ int launch_collide(lbm_ctx* c, MomOut mo) {
                                  S_plane<T>(c));
 }
 
-int launch_reduce(lbm_ctx* c, int slot) {
-  const long long n = (long long)c->ntx2 * c->nty2;
+template <typename T, int MODE, bool WRITE_PHIMU>
+int launch_fused(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
+  hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU>), dim3(c->ntxf * c->ntyf), dim3(FS_W), 0, c->stream,
+                     c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf);
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
+int launch_reduce(lbm_ctx* c, int slot, long long n) {
   const long long chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
   const long long nb = (n + chunk - 1) / chunk;
   hipLaunchKernelGGL(k_reduce_diag, dim3((unsigned)nb), dim3(256), 0, c->stream, c->partials, n, chunk,
@@ -237,33 +249,43 @@ int consume_diag(lbm_ctx* c, bool wait) {
   return LBM_OK;
 }
 
+// One step.  kernel_path 0: the fused kernel (phi and mu stay in LDS);
+// 1: the phi/mu pass then the collide-stream pass.
+template <typename T>
+int launch_step(lbm_ctx* c, bool diag) {
+  if (c->fused) {
+    T* Bin = popbuf<T>(c, c->cur);
+    T* Bout = popbuf<T>(c, c->cur ^ 1);
+    return diag ? launch_fused<T, M_STEP_DIAG, false>(c, Bin, Bout, S_plane<T>(c), S_plane<T>(c), nullptr, nullptr)
+                : launch_fused<T, M_STEP, false>(c, Bin, Bout, S_plane<T>(c), S_plane<T>(c), nullptr, nullptr);
+  }
+  int r = launch_phi_mu<T>(c);
+  if (r) return r;
+  return diag ? launch_collide<T, M_STEP_DIAG>(c, MomOut{}) : launch_collide<T, M_STEP>(c, MomOut{});
+}
+
 template <typename T>
 int step_impl(lbm_ctx* c, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const bool diag = c->p.diag_every > 0 && (c->step % c->p.diag_every) == 0;
     if (c->timing) {
-      hipEvent_t e[3];
-      for (int j = 0; j < 3; ++j) {
+      hipEvent_t e[2];
+      for (int j = 0; j < 2; ++j) {
         HIPCHK(c, hipEventCreate(&e[j]));
         c->tev.push_back(e[j]);
       }
       HIPCHK(c, hipEventRecord(e[0], c->stream));
-      int r = launch_phi_mu<T>(c);
+      int r = launch_step<T>(c, diag);
       if (r) return r;
       HIPCHK(c, hipEventRecord(e[1], c->stream));
-      r = diag ? launch_collide<T, M_STEP_DIAG>(c, MomOut{}) : launch_collide<T, M_STEP>(c, MomOut{});
-      if (r) return r;
-      HIPCHK(c, hipEventRecord(e[2], c->stream));
     } else {
-      int r = launch_phi_mu<T>(c);
-      if (r) return r;
-      r = diag ? launch_collide<T, M_STEP_DIAG>(c, MomOut{}) : launch_collide<T, M_STEP>(c, MomOut{});
+      int r = launch_step<T>(c, diag);
       if (r) return r;
     }
     if (diag) {
       int r = consume_diag(c, true);  // the host buffer is about to be reused
       if (r) return r;
-      r = launch_reduce(c, 0);
+      r = launch_reduce(c, 0, c->fused ? (long long)c->ntxf * c->ntyf : (long long)c->ntx2 * c->nty2);
       if (r) return r;
       HIPCHK(c, hipMemcpyAsync(c->diag_host, c->diag_dev, NQ * sizeof(double),
                                hipMemcpyDeviceToHost, c->stream));
@@ -298,7 +320,7 @@ int moments_impl(lbm_ctx* c, MomOut mo, lbm_diag* diag) {
   r = launch_collide<T, M_MOMENTS>(c, mo);
   if (r) return r;
   if (diag) {
-    r = launch_reduce(c, 1);
+    r = launch_reduce(c, 1, (long long)c->ntx2 * c->nty2);
     if (r) return r;
     HIPCHK(c, hipMemcpyAsync(c->diag_host + NQ, c->diag_dev + NQ, NQ * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
@@ -352,6 +374,9 @@ T* snap_mu(const lbm_ctx* c, const T* snap) {
 
 template <typename T>
 int step_into_impl(lbm_ctx* c, T* src, T* dst) {
+  if (c->fused)
+    return launch_fused<T, M_STEP, true>(c, src, dst, snap_S(c, src), snap_S(c, dst), snap_dphi(c, src),
+                                         snap_mu(c, src));
   hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, src,
                      nullptr, snap_dphi(c, src), snap_mu(c, src), c->ntx1);
   LAUNCHCHK(c);
@@ -477,6 +502,9 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   c->nty1 = L.nty1;
   c->ntx2 = L.ntx2;
   c->nty2 = L.nty2;
+  c->ntxf = (p->nx + FS_W - 1) / FS_W;
+  c->ntyf = (p->ny + FS_H - 1) / FS_H;
+  c->fused = p->kernel_path == 0;
   c->partials = reinterpret_cast<double*>(c->ws);
   c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
   c->diag_dev = c->red_mid + (size_t)RED_BLOCKS * NQ;
@@ -585,20 +613,17 @@ int lbm_timing(lbm_ctx* c, int enable) {
   return LBM_OK;
 }
 
-int lbm_kernel_times(lbm_ctx* c, double* ms_phi_mu, double* ms_collide, int64_t* steps) {
+int lbm_kernel_times(lbm_ctx* c, double* ms_step, int64_t* steps) {
   if (!c) return LBM_EINVAL;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double a = 0.0, b = 0.0;
-  for (size_t k = 0; k + 2 < c->tev.size(); k += 3) {
-    float t1 = 0.f, t2 = 0.f;
-    HIPCHK(c, hipEventElapsedTime(&t1, c->tev[k], c->tev[k + 1]));
-    HIPCHK(c, hipEventElapsedTime(&t2, c->tev[k + 1], c->tev[k + 2]));
-    a += t1;
-    b += t2;
+  double a = 0.0;
+  for (size_t k = 0; k + 1 < c->tev.size(); k += 2) {
+    float t = 0.f;
+    HIPCHK(c, hipEventElapsedTime(&t, c->tev[k], c->tev[k + 1]));
+    a += t;
   }
-  if (ms_phi_mu) *ms_phi_mu = a;
-  if (ms_collide) *ms_collide = b;
-  if (steps) *steps = (int64_t)(c->tev.size() / 3);
+  if (ms_step) *ms_step = a;
+  if (steps) *steps = (int64_t)(c->tev.size() / 2);
   return LBM_OK;
 }
 

@@ -23,7 +23,7 @@ def make_params(workload=None, precision: int = 64, diag_every: int = 0, **over)
     kw = dict(nx=0, ny=0, bc_x=0, bc_y=0, precision=precision, use_sigma_W=0, phi_A=1.0,
               phi_B=-1.0, rho_A=1.0, rho_B=1.0, nu_A=0.1, nu_B=0.1, kappa=0.0, beta=0.0,
               sigma=0.0, W=0.0, M=0.1, alpha=1.0, gx=0.0, gy=0.0, diag_every=diag_every,
-              reserved=0)
+              kernel_path=0)
     if workload is not None:
         for k in ("nx", "ny", "bc_x", "bc_y", "phi_A", "phi_B", "rho_A", "rho_B", "nu_A", "nu_B",
                   "sigma", "W", "M", "alpha"):
@@ -155,10 +155,11 @@ class Sim:
         check(self.L.lbm_timing(self.ctx, int(bool(enable))), "lbm_timing", self.ctx)
 
     def kernel_times(self):
-        a, b, n = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
-        check(self.L.lbm_kernel_times(self.ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(n)),
+        """(summed ms of the timed steps' kernels, number of steps)."""
+        a, n = ctypes.c_double(), ctypes.c_int64()
+        check(self.L.lbm_kernel_times(self.ctx, ctypes.byref(a), ctypes.byref(n)),
               "lbm_kernel_times", self.ctx)
-        return a.value, b.value, n.value
+        return a.value, n.value
 
     # -- snapshots (raw state) ----------------------------------------------
 

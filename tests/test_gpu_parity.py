@@ -12,6 +12,8 @@ import sys
 import numpy as np
 import pytest
 
+import torch
+
 import equilibrium
 import oracle
 from harness import compare_moments, compare_state, gpu_moments, gpu_sim, gpu_state, oracle_sim, rel
@@ -300,3 +302,34 @@ def test_full_size_sampled(prec):
             for a, b, fl in zip(gst, ost, floors):
                 scale = max(np.abs(b[c]).max(), 1e-30 if prec == 64 else fl)
                 assert np.abs(a[c] - b[c]).max() <= tol * scale, (prec, nsteps, w)
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("name", ["flat", "ragged_walls", "ragged_periodic", "tiny_walls", "one_column"])
+def test_fused_and_two_kernel_paths_agree_bitwise(prec, name):
+    # kernel_path 0 (phi and mu in LDS) and 1 (two kernels) give the same bits.
+    wl, phi0, over = _case(name)
+    say(f"[gpu] fused vs two-kernel {name} prec={prec}")
+    a = gpu_sim(wl, phi0, prec, kernel_path=0, diag_every=7, **over).step(150)
+    b = gpu_sim(wl, phi0, prec, kernel_path=1, diag_every=7, **over).step(150)
+    for x, y in zip(gpu_state(a), gpu_state(b)):
+        assert np.array_equal(x, y)
+    da, db = a.last_diag(), b.last_diag()
+    assert da["step"] == db["step"] == 147 and da["n_nonfinite"] == 0
+    assert da["sum_phi"] == pytest.approx(db["sum_phi"], rel=1e-13, abs=1e-13)
+
+
+def test_fused_step_into_writes_phi_mu_for_the_adjoint():
+    # lbm_step_into leaves phi and mu of its source in the snapshot; the
+    # adjoint with and without that shortcut gives the same lambda.
+    wl, phi0, over = _case("ragged_walls")
+    g = gpu_sim(wl, phi0, 64, **over)
+    g.enable_adjoint()
+    s0, s1 = g.snapshot(), g.new_snapshot()
+    g.step_into(s0, s1)
+    lam = g.new_adjoint()
+    lam.normal_()
+    o1, o2 = g.new_adjoint(), g.new_adjoint()
+    g.adjoint_step(s0, lam, o1, have_phi_mu=True)
+    g.adjoint_step(s0, lam, o2, have_phi_mu=False)
+    assert torch.equal(o1, o2)
