@@ -109,7 +109,8 @@ struct Pops {
   T lo;  // FP32 only: low word of f_0
 };
 
-template <bool WITH_G, typename T>
+// WITH_G: also gather g.  WITH_F: gather f (and the low word of f_0).
+template <bool WITH_G, typename T, bool WITH_F = true>
 __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int x, int y, Pops<T>& q) {
   const PullCols px = pull_cols(x, p.nx, p.bcx);
   const PullCols py = pull_cols(y, p.ny, p.bcy);
@@ -128,10 +129,10 @@ __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int
       plane = i;
       off = (long long)sy * p.pitch + sx;
     }
-    q.f[i] = B[plane * p.ps + off];
+    if (WITH_F) q.f[i] = B[plane * p.ps + off];
     if (WITH_G) q.g[i] = B[(9 + plane) * p.ps + off];
   }
-  if (std::is_same<T, float>::value) q.lo = B[LO_PLANE * p.ps + own];
+  if (WITH_F && std::is_same<T, float>::value) q.lo = B[LO_PLANE * p.ps + own];
 }
 
 // Store one pre-collision population so that the pull gather returns it:

@@ -393,19 +393,36 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
 // only on n, so the result is bitwise reproducible.
 constexpr int RED_BLOCKS = 1024;
 // ------------------------------------------- fused step: phi, mu, collide
-// One workgroup owns a strip of FS_W columns and FS_H rows and marches up
-// it.  Per row y it gathers phi of row y+2 (5-row ring in LDS, FS_W + 4
-// columns), computes mu of row y+1 (3-row ring, FS_W + 2 columns) and then
-// collides row y with the same arithmetic as k_collide, reading the 3x3 phi
-// and mu from LDS.  phi and mu never go to HBM unless WRITE_PHIMU asks for
-// them (the adjoint's recompute keeps them).  Same results as k_phi_mu +
-// k_collide, bit for bit.
+// One workgroup owns a strip of W columns and H rows and marches up it.
+// Per row y it gathers f at row y+2 for phi (5-row ring in LDS, W + 4
+// columns) and keeps the strip's own gathered f (4-row ring), computes mu of
+// row y+1 (3-row ring, W + 2 columns) and then collides row y with the same
+// arithmetic as k_collide: f and the 3x3 phi and mu come from LDS, only g is
+// gathered from memory.  Every population plane is read from HBM once (up
+// to the ring recompute at strip edges); phi and mu never go to HBM unless
+// WRITE_PHIMU asks for them (the adjoint's recompute keeps them).  Same
+// results as k_phi_mu + k_collide, bit for bit.
 //
 // Ghosts: ring entries outside the grid hold phi of the wrapped or mirrored
 // cell; a mu entry just outside a wall holds mu of the adjacent cell (its
 // stencil is shifted by one), which is what the two-kernel path reads
 // through stencil_idx.
-constexpr int FS_W = 256, FS_H = 64;
+// Strip width (= threads per workgroup) and height.
+template <typename T>
+struct Strip;
+// KEEP_F: keep the strip's gathered f in LDS for the collision (FP32);
+// FP64 re-gathers f instead, since the FP64 ring would leave room for one
+// workgroup per CU.
+template <>
+struct Strip<float> {
+  static constexpr int W = 256, H = 64;
+  static constexpr bool KEEP_F = true;
+};
+template <>
+struct Strip<double> {
+  static constexpr int W = 256, H = 64;
+  static constexpr bool KEEP_F = false;
+};
 
 __device__ __forceinline__ int mod_pos(int a, int m) {
   const int r = a % m;
@@ -413,39 +430,53 @@ __device__ __forceinline__ int mod_pos(int a, int m) {
 }
 
 template <typename T, int MODE, bool WRITE_PHIMU>
-__global__ __launch_bounds__(FS_W) void k_step_fused(const KP p, const T* Bin, T* Bout, const T* Spin,
-                                                      T* Spout, T* __restrict__ dphi_out,
-                                                      T* __restrict__ mu_out, double* __restrict__ partials,
-                                                      int ntx) {
+__global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T* Bin, T* Bout, const T* Spin,
+                                                             T* Spout, T* __restrict__ dphi_out,
+                                                             T* __restrict__ mu_out,
+                                                             double* __restrict__ partials, int ntx) {
   constexpr bool DIAG = MODE == M_STEP_DIAG;
-  __shared__ T phr[5][FS_W + 4];  // column x0 - 2 + k
-  __shared__ T mur[3][FS_W + 2];  // column x0 - 1 + k
+  constexpr int W = Strip<T>::W, H = Strip<T>::H;
+  constexpr bool KEEP_F = Strip<T>::KEEP_F;
+  constexpr int NF = std::is_same<T, float>::value ? 10 : 9;  // f_0..f_8 (+ low word of f_0)
+  __shared__ T phr[5][W + 4];                  // phi - phi_ref, column x0 - 2 + k
+  __shared__ T mur[3][W + 2];                  // mu, column x0 - 1 + k
+  __shared__ T fr[KEEP_F ? 4 : 1][NF][W];      // gathered f of the strip's own columns
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (blk % ntx) * FS_W, y0 = (blk / ntx) * FS_H;
-  const int y1 = y0 + FS_H < p.ny ? y0 + FS_H : p.ny;
+  const int x0 = (blk % ntx) * W, y0 = (blk / ntx) * H;
+  const int y1 = y0 + H < p.ny ? y0 + H : p.ny;
   const int t = threadIdx.x;
 
+  // phi of row yu (unwrapped) on W + 4 columns; for rows this strip collides
+  // the gathered f of its own columns is kept for the collision.
   auto phi_row = [&](int yu) {
     const int gy = stencil_idx(yu, p.ny, p.bcy);
     T* row = phr[mod_pos(yu, 5)];
-    for (int k = t; k < FS_W + 4; k += FS_W) {
+    const bool keep = yu >= y0 && yu < y1;
+    T(*fk)[W] = fr[KEEP_F ? mod_pos(yu, 4) : 0];
+    for (int k = t; k < W + 4; k += W) {
       const int gx = stencil_idx(x0 - 2 + k, p.nx, p.bcx);
       Pops<T> q;
       gather<false>(Bin, p, gx, gy, q);
       const T v = phi_sum<T>(q);
       row[k] = v;
-      if (WRITE_PHIMU && yu >= y0 && yu < y1 && k >= 2 && k < FS_W + 2 && x0 - 2 + k < p.nx)
-        dphi_out[(long long)yu * p.pitch + (x0 - 2 + k)] = v;
+      if (keep && k >= 2 && k < W + 2) {
+        if constexpr (KEEP_F) {
+#pragma unroll
+          for (int i = 0; i < 9; ++i) fk[i][k - 2] = q.f[i];
+          if constexpr (NF == 10) fk[9][k - 2] = q.lo;
+        }
+        if (WRITE_PHIMU && x0 - 2 + k < p.nx) dphi_out[(long long)yu * p.pitch + (x0 - 2 + k)] = v;
+      }
     }
   };
   auto mu_row = [&](int yu) {
-    // rows used by the stencil: shifted inward for a ghost row beyond a wall
+    // stencil rows shifted inward for a ghost row beyond a wall
     const int sy = p.bcy ? (yu < 0 ? 1 : (yu >= p.ny ? -1 : 0)) : 0;
     const T* r0 = phr[mod_pos(yu + sy - 1, 5)];
     const T* r1 = phr[mod_pos(yu + sy, 5)];
     const T* r2 = phr[mod_pos(yu + sy + 1, 5)];
     T* out = mur[mod_pos(yu, 3)];
-    for (int k = t; k < FS_W + 2; k += FS_W) {
+    for (int k = t; k < W + 2; k += W) {
       const int xu = x0 - 1 + k;
       const int sx = p.bcx ? (xu < 0 ? 1 : (xu >= p.nx ? -1 : 0)) : 0;
       const int c = k + 1 + sx;  // phi ring index of the stencil centre
@@ -453,7 +484,7 @@ __global__ __launch_bounds__(FS_W) void k_step_fused(const KP p, const T* Bin, T
                          {r2[c - 1], r2[c], r2[c + 1]}};
       const T m = mu_cell<T>(p, v);
       out[k] = m;
-      if (WRITE_PHIMU && yu >= y0 && yu < y1 && k >= 1 && k <= FS_W && xu < p.nx)
+      if (WRITE_PHIMU && yu >= y0 && yu < y1 && k >= 1 && k <= W && xu < p.nx)
         mu_out[(long long)yu * p.pitch + xu] = m;
     }
   };
@@ -465,15 +496,37 @@ __global__ __launch_bounds__(FS_W) void k_step_fused(const KP p, const T* Bin, T
   mu_row(y0 - 1);
   mu_row(y0);
   const int x = x0 + t;
+  // Ring hazards: phi_row(y+2) overwrites the phi slot of row y-3 and the f
+  // slot of row y-2, whose last readers (mu_row(y-2), the collision of row
+  // y-2) finished before the barriers of iteration y-1; mu_row(y+1)
+  // overwrites the slot of row y-2, read last by the collision of row y-1,
+  // which finished before the first barrier of iteration y.
   for (int y = y0; y < y1; ++y) {
+    // Without the f ring (FP64) this row's f, g and S_prev loads are issued
+    // first, so they are in flight across the phi/mu work and the barriers;
+    // with it (FP32) they are issued after the barriers, where the smaller
+    // register footprint keeps more waves resident.
+    const bool active = x < p.nx;
+    const long long o = (long long)y * p.pitch + x;
+    Pops<T> q;
+    T Sp = T(0);
+    if (!KEEP_F && active) {
+      gather<true, T, true>(Bin, p, x, y, q);
+      Sp = Spin[o];
+    }
     phi_row(y + 2);
     __syncthreads();
     mu_row(y + 1);
     __syncthreads();
-    if (x < p.nx) {
-      const long long o = (long long)y * p.pitch + x;
-      Pops<T> q;
-      gather<true>(Bin, p, x, y, q);
+    if (active) {
+      if constexpr (KEEP_F) {
+        gather<true, T, false>(Bin, p, x, y, q);  // g from memory, f from LDS
+        Sp = Spin[o];
+        T(*fk)[W] = fr[mod_pos(y, 4)];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) q.f[i] = fk[i][t];
+        if constexpr (NF == 10) q.lo = fk[9][t];
+      }
       Nbhd<T> nb;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
@@ -485,7 +538,6 @@ __global__ __launch_bounds__(FS_W) void k_step_fused(const KP p, const T* Bin, T
           nb.mu[a][b] = mr[t + b];
         }
       }
-      const T Sp = Spin[o];
       T fo[9], go[9];
       T lo = 0;
       CellOut c;
@@ -493,13 +545,14 @@ __global__ __launch_bounds__(FS_W) void k_step_fused(const KP p, const T* Bin, T
         cell_f64<true>(p, q, nb, Sp, fo, go, c);
       else
         cell_f32<true>(p, q, nb, Sp, fo, lo, go, c);
+      // streaming stores: nothing reads them before they leave the caches
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        Bout[i * p.ps + o] = fo[i];
-        Bout[(9 + i) * p.ps + o] = go[i];
+        __builtin_nontemporal_store(fo[i], Bout + i * p.ps + o);
+        __builtin_nontemporal_store(go[i], Bout + (9 + i) * p.ps + o);
       }
-      if constexpr (std::is_same<T, float>::value) Bout[LO_PLANE * p.ps + o] = lo;
-      Spout[o] = (T)c.S;
+      if constexpr (std::is_same<T, float>::value) __builtin_nontemporal_store(lo, Bout + LO_PLANE * p.ps + o);
+      __builtin_nontemporal_store((T)c.S, Spout + o);
       if (DIAG) {
         const bool fin = isfinite(c.phi) && isfinite(c.mu) && isfinite(c.ux) && isfinite(c.uy) &&
                          isfinite(c.p);

@@ -195,8 +195,8 @@ int launch_collide(lbm_ctx* c, MomOut mo) {
 
 template <typename T, int MODE, bool WRITE_PHIMU>
 int launch_fused(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
-  hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU>), dim3(c->ntxf * c->ntyf), dim3(FS_W), 0, c->stream,
-                     c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf);
+  hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU>), dim3(c->ntxf * c->ntyf), dim3(Strip<T>::W), 0,
+                     c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf);
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -502,8 +502,12 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   c->nty1 = L.nty1;
   c->ntx2 = L.ntx2;
   c->nty2 = L.nty2;
-  c->ntxf = (p->nx + FS_W - 1) / FS_W;
-  c->ntyf = (p->ny + FS_H - 1) / FS_H;
+  {
+    const int sw = p->precision == 32 ? Strip<float>::W : Strip<double>::W;
+    const int sh = p->precision == 32 ? Strip<float>::H : Strip<double>::H;
+    c->ntxf = (p->nx + sw - 1) / sw;
+    c->ntyf = (p->ny + sh - 1) / sh;
+  }
   c->fused = p->kernel_path == 0;
   c->partials = reinterpret_cast<double*>(c->ws);
   c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
