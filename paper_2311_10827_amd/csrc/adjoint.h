@@ -34,8 +34,8 @@ constexpr int NTH = 6;  // kappa, beta, alpha, tau_f, nu_A, nu_B
 // Cells x with neighbour(x + c) == v along one axis (c in {-1, 0, 1}).
 __device__ __forceinline__ int preimages(int v, int c, int n, int wall, int (&out)[2]) {
   if (!wall) {
-    int r = (v - c) % n;
-    out[0] = r < 0 ? r + n : r;
+    const int r = v - c;
+    out[0] = r < 0 ? r + n : (r >= n ? r - n : r);
     return 1;
   }
   if (c == 0) {
@@ -70,10 +70,14 @@ __device__ __forceinline__ A grad_T(const KP& p, const T* __restrict__ wx, const
                                     int y) {
   A acc = A(0);
   if (single_pre(x, p.nx, p.bcx) && single_pre(y, p.ny, p.bcy)) {
+    // an axis direction has one non-zero component: read only that plane
 #pragma unroll
     for (int d = 1; d < 9; ++d) {
-      const long long k = (long long)pre1(y, cy_of(d), p.ny) * p.nx + pre1(x, cx_of(d), p.nx);
-      acc += A(INV_CS2 * w_of(d)) * (A(cx_of(d)) * A(wx[k]) + A(cy_of(d)) * A(wy[k]));
+      const unsigned k = (unsigned)(pre1(y, cy_of(d), p.ny) * p.nx + pre1(x, cx_of(d), p.nx));
+      const A t = cy_of(d) == 0   ? A(cx_of(d)) * A(wx[k])
+                  : cx_of(d) == 0 ? A(cy_of(d)) * A(wy[k])
+                                  : A(cx_of(d)) * A(wx[k]) + A(cy_of(d)) * A(wy[k]);
+      acc += A(INV_CS2 * w_of(d)) * t;
     }
     return acc;
   }
@@ -85,7 +89,7 @@ __device__ __forceinline__ A grad_T(const KP& p, const T* __restrict__ wx, const
     const A k3 = A(INV_CS2 * w_of(d));
     for (int a = 0; a < nyp; ++a)
       for (int b = 0; b < nxp; ++b) {
-        const long long k = (long long)py[a] * p.nx + px[b];
+        const unsigned k = (unsigned)(py[a] * p.nx + px[b]);
         acc += k3 * (A(cx_of(d)) * A(wx[k]) + A(cy_of(d)) * A(wy[k]));
       }
   }
@@ -100,8 +104,8 @@ __device__ __forceinline__ double lap_T(const KP& p, const T* __restrict__ w, in
 #pragma unroll
     for (int d = 1; d < 9; ++d)
       acc += (2.0 * INV_CS2 * w_of(d)) *
-             (double)w[(long long)pre1(y, cy_of(d), p.ny) * p.nx + pre1(x, cx_of(d), p.nx)];
-    return acc - (2.0 * INV_CS2 * (1.0 - w_of(0))) * (double)w[(long long)y * p.nx + x];
+             (double)w[(unsigned)(pre1(y, cy_of(d), p.ny) * p.nx + pre1(x, cx_of(d), p.nx))];
+    return acc - (2.0 * INV_CS2 * (1.0 - w_of(0))) * (double)w[(unsigned)(y * p.nx + x)];
   }
 #pragma unroll
   for (int d = 1; d < 9; ++d) {
@@ -110,28 +114,31 @@ __device__ __forceinline__ double lap_T(const KP& p, const T* __restrict__ w, in
     const int nyp = preimages(y, cy_of(d), p.ny, p.bcy, py);
     const double l = 2.0 * INV_CS2 * w_of(d);
     for (int a = 0; a < nyp; ++a)
-      for (int b = 0; b < nxp; ++b) acc += l * (double)w[(long long)py[a] * p.nx + px[b]];
+      for (int b = 0; b < nxp; ++b) acc += l * (double)w[(unsigned)(py[a] * p.nx + px[b])];
   }
-  return acc - (2.0 * INV_CS2 * (1.0 - w_of(0))) * (double)w[(long long)y * p.nx + x];
+  return acc - (2.0 * INV_CS2 * (1.0 - w_of(0))) * (double)w[(unsigned)(y * p.nx + x)];
 }
 
 // Forward Laplacian of phi from the dphi plane (3x3 with the forward rule).
-__device__ __forceinline__ double lap_fwd(const double (&v)[3][3]) {
-  const double c = v[1][1];
-  return (2.0 / 3.0) * (((v[1][2] - c) + (v[1][0] - c)) + ((v[2][1] - c) + (v[0][1] - c))) +
-         (1.0 / 6.0) * (((v[2][2] - c) + (v[2][0] - c)) + ((v[0][2] - c) + (v[0][0] - c)));
+template <typename A>
+__device__ __forceinline__ A lap_fwd(const A (&v)[3][3]) {
+  const A c = v[1][1];
+  return A(2.0 / 3.0) * (((v[1][2] - c) + (v[1][0] - c)) + ((v[2][1] - c) + (v[0][1] - c))) +
+         A(1.0 / 6.0) * (((v[2][2] - c) + (v[2][0] - c)) + ((v[0][2] - c) + (v[0][0] - c)));
 }
 __device__ __forceinline__ void grad_fwd(const double (&v)[3][3], double& gx, double& gy) {
   gx = (1.0 / 3.0) * (v[1][2] - v[1][0]) + (1.0 / 12.0) * ((v[2][2] - v[2][0]) + (v[0][2] - v[0][0]));
   gy = (1.0 / 3.0) * (v[2][1] - v[0][1]) + (1.0 / 12.0) * ((v[2][2] - v[0][2]) + (v[2][0] - v[0][0]));
 }
 // psi'(phi) / beta and psi''(phi) / beta for psi = beta (phi - A)^2 (phi - B)^2.
-__device__ __forceinline__ double dpsi_b(const KP& p, double ph) {
-  return 4.0 * (ph - p.phiA) * (ph - p.phiB) * (ph - p.phim);
+template <typename A>
+__device__ __forceinline__ A dpsi_b(const KP& p, A ph) {
+  return A(4.0) * (ph - A(p.phiA)) * (ph - A(p.phiB)) * (ph - A(p.phim));
 }
-__device__ __forceinline__ double d2psi_b(const KP& p, double ph) {
-  const double a = ph - p.phiA, b = ph - p.phiB, m = ph - p.phim;
-  return 4.0 * (a * b + a * m + b * m);
+template <typename A>
+__device__ __forceinline__ A d2psi_b(const KP& p, A ph) {
+  const A a = ph - A(p.phiA), b = ph - A(p.phiB), m = ph - A(p.phim);
+  return A(4.0) * (a * b + a * m + b * m);
 }
 
 // Sum-reduce NV values over the block and add them to out[0..NV) (the
@@ -185,8 +192,8 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
   const int y = (tile / ntx) * K2_TY + threadIdx.x / K2_TX;
   double th[4] = {0.0, 0.0, 0.0, 0.0};  // alpha, tau_f, nu_A, nu_B
   if (x < p.nx && y < p.ny) {
-    const long long n = (long long)p.nx * p.ny;
-    const long long kd = (long long)y * p.nx + x;
+    const long long n = (long long)p.nx * p.ny;  // plane stride of the dense planes
+    const unsigned kd = (unsigned)(y * p.nx + x);  // n <= INT32_MAX
     const C half = C(0.5), one = C(1.0), three = C(3.0);
     // ---- forward recompute at this cell
     Pops<T> q;
@@ -243,22 +250,16 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
       for (int j = 0; j < 9; ++j) {
         int tx = x + cx_of(j), ty = y + cy_of(j);
         const bool wall = (p.bcx && (tx < 0 || tx >= p.nx)) || (p.bcy && (ty < 0 || ty >= p.ny));
-        long long k;
-        int pl;
-        if (wall) {
-          k = kd;
-          pl = opp_of(j);
-        } else {
-          tx = tx < 0 ? tx + p.nx : (tx >= p.nx ? tx - p.nx : tx);
-          ty = ty < 0 ? ty + p.ny : (ty >= p.ny ? ty - p.ny : ty);
-          k = (long long)ty * p.nx + tx;
-          pl = j;
-        }
-        a[j] = lam_in[pl * n + k];
-        c[j] = lam_in[(9 + pl) * n + k];
+        tx = tx < 0 ? tx + p.nx : (tx >= p.nx ? tx - p.nx : tx);
+        ty = ty < 0 ? ty + p.ny : (ty >= p.ny ? ty - p.ny : ty);
+        const unsigned k = wall ? kd : (unsigned)(ty * p.nx + tx);
+        const T* la = wall ? lam_in + opp_of(j) * n : lam_in + j * n;
+        const T* lc = wall ? lam_in + (9 + opp_of(j)) * n : lam_in + (9 + j) * n;
+        a[j] = la[k];
+        c[j] = lc[k];
       }
     }
-    lS = lam_in[18 * n + kd];  // S_prev(n+1) = S(n): no streaming
+    lS = (lam_in + 18 * n)[kd];  // S_prev(n+1) = S(n): no streaming
 
     // ---- order-parameter collision: f* = f - w_f (f - f^eq) + w b (3/2 S - 1/2 S_prev)
     const C wf = C(p.omega_f), alpha = C(p.alpha);
@@ -340,8 +341,8 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
     // ---- outputs
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      lam_out[(9 + i) * n + kd] = (one - wg) * c[i] + C(cx_of(i)) * lmx + C(cy_of(i)) * lmy + (i ? lsnz : C(0));
-    lam_out[18 * n + kd] = INIT ? C(0) : lSp_out;
+      (lam_out + (9 + i) * n)[kd] = (one - wg) * c[i] + C(cx_of(i)) * lmx + C(cy_of(i)) * lmy + (i ? lsnz : C(0));
+    (lam_out + 18 * n)[kd] = INIT ? C(0) : lSp_out;
     w.lphi[kd] = lphi;
     w.lmu[kd] = lmu;
     w.lgpx[kd] = lgpx;
@@ -377,15 +378,20 @@ __device__ __forceinline__ int pre_off(int v, int c, int n, int wall, int (&out)
   return k;
 }
 
+// Tiles of KM_TX x KM_TY cells (256 threads, KM_TY / 4 rows each): the
+// one-cell ring of lambda_mu_tot, recomputed by each tile, is 16 % of the
+// tile's cells.
+constexpr int KM_TX = 64, KM_TY = 16;
+
 template <typename T, bool INIT>
 __global__ __launch_bounds__(256) void ka_mu_phi(const KP p, const T* __restrict__ dphi,
                                                   const T* __restrict__ lam_in, T* __restrict__ lam_out,
                                                   AdjWork<T> w, double* __restrict__ th_part, int ntx) {
   using C = T;  // arithmetic in the storage type, as in ka_local
-  constexpr int LW = K2_TX + 2, LH = K2_TY + 2;
+  constexpr int LW = KM_TX + 2, LH = KM_TY + 2;
   __shared__ C mt[LH][LW];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int x0 = (tile % ntx) * K2_TX, y0 = (tile / ntx) * K2_TY;
+  const int x0 = (tile % ntx) * KM_TX, y0 = (tile / ntx) * KM_TY;
   for (int k = threadIdx.x; k < LH * LW; k += blockDim.x) {
     const int ly = k / LW, lx = k - ly * LW;
     int gx = x0 + lx - 1, gy = y0 + ly - 1;
@@ -394,17 +400,19 @@ __global__ __launch_bounds__(256) void ka_mu_phi(const KP p, const T* __restrict
     if (!((outx && p.bcx) || (outy && p.bcy))) {
       gx = stencil_idx(gx, p.nx, 0);
       gy = stencil_idx(gy, p.ny, 0);
-      v = w.lmu[(long long)gy * p.nx + gx] + grad_T<C>(p, w.lgmx, w.lgmy, gx, gy);
+      v = w.lmu[(unsigned)(gy * p.nx + gx)] + grad_T<C>(p, w.lgmx, w.lgmy, gx, gy);
     }
     mt[ly][lx] = v;
   }
   __syncthreads();
-  const int tx = threadIdx.x & (K2_TX - 1), ty = threadIdx.x / K2_TX;
-  const int x = x0 + tx, y = y0 + ty;
+  const long long n = (long long)p.nx * p.ny;
+  const int tx = threadIdx.x & (KM_TX - 1);
+  const int x = x0 + tx;
   double th[2] = {0.0, 0.0};  // kappa, beta
-  if (x < p.nx && y < p.ny) {
-    const long long n = (long long)p.nx * p.ny;
-    const long long kd = (long long)y * p.nx + x;
+  for (int ty = threadIdx.x / KM_TX; ty < KM_TY; ty += 256 / KM_TX) {
+    const int y = y0 + ty;
+    if (x >= p.nx || y >= p.ny) continue;
+    const unsigned kd = (unsigned)(y * p.nx + x);
     const int lx = tx + 1, ly = ty + 1;
     const C lmt = mt[ly][lx];
     // L^T lambda_mu_tot from LDS
@@ -424,18 +432,18 @@ __global__ __launch_bounds__(256) void ka_mu_phi(const KP p, const T* __restrict
     }
     lt -= C(2.0 * INV_CS2 * (1.0 - w_of(0))) * lmt;
     // forward phi around the cell for lap(phi) and psi
-    double v[3][3];
+    C v[3][3];
     const int xs[3] = {stencil_idx(x - 1, p.nx, p.bcx), x, stencil_idx(x + 1, p.nx, p.bcx)};
     const int ys[3] = {stencil_idx(y - 1, p.ny, p.bcy), y, stencil_idx(y + 1, p.ny, p.bcy)};
 #pragma unroll
     for (int a = 0; a < 3; ++a)
 #pragma unroll
-      for (int b = 0; b < 3; ++b) v[a][b] = (double)dphi[(long long)ys[a] * p.pitch + xs[b]] + p.phi_ref;
-    const double ph = v[1][1];
-    th[0] = -lap_fwd(v) * (double)lmt;  // mu = psi'(phi) - kappa lap(phi)
-    th[1] = dpsi_b(p, ph) * (double)lmt;
+      for (int b = 0; b < 3; ++b) v[a][b] = dphi[(unsigned)(ys[a] * p.pitch + xs[b])] + C(p.phi_ref);
+    const C ph = v[1][1];
+    th[0] += (double)(-lap_fwd<C>(v) * lmt);  // mu = psi'(phi) - kappa lap(phi)
+    th[1] += (double)(dpsi_b<C>(p, ph) * lmt);
     const C lphi = w.lphi[kd] + grad_T<C>(p, w.lgpx, w.lgpy, x, y) +
-                   C(p.beta4 * 0.25 * d2psi_b(p, ph)) * lmt - C(p.kappa) * lt;
+                   C(p.beta4 * 0.25) * d2psi_b<C>(p, ph) * lmt - C(p.kappa) * lt;
     const C k1 = C(1.0 - p.omega_f);
 #pragma unroll
     for (int j = 0; j < 9; ++j) {
@@ -443,15 +451,13 @@ __global__ __launch_bounds__(256) void ka_mu_phi(const KP p, const T* __restrict
       if (!INIT) {
         int qx = x + cx_of(j), qy = y + cy_of(j);
         const bool wall = (p.bcx && (qx < 0 || qx >= p.nx)) || (p.bcy && (qy < 0 || qy >= p.ny));
-        if (wall) {
-          a = lam_in[opp_of(j) * n + kd];
-        } else {
-          qx = qx < 0 ? qx + p.nx : (qx >= p.nx ? qx - p.nx : qx);
-          qy = qy < 0 ? qy + p.ny : (qy >= p.ny ? qy - p.ny : qy);
-          a = lam_in[j * n + (long long)qy * p.nx + qx];
-        }
+        qx = qx < 0 ? qx + p.nx : (qx >= p.nx ? qx - p.nx : qx);
+        qy = qy < 0 ? qy + p.ny : (qy >= p.ny ? qy - p.ny : qy);
+        const unsigned k = wall ? kd : (unsigned)(qy * p.nx + qx);
+        const T* la = wall ? lam_in + opp_of(j) * n : lam_in + j * n;
+        a = la[k];
       }
-      lam_out[j * n + kd] = k1 * a + lphi;
+      (lam_out + j * n)[kd] = k1 * a + lphi;
     }
   }
   block_sum_add<2>(th, th_part + (long long)tile * NTH + 0);
@@ -503,10 +509,10 @@ __global__ __launch_bounds__(256) void ki_phi(const KP p, const double* __restri
     for (int a = 0; a < 3; ++a)
       for (int b = 0; b < 3; ++b) v[a][b] = phi0[(long long)ys[a] * p.nx + xs[b]];
     const double lm = (double)w.lmu_tot[kd];
-    dphi0[kd] = (double)w.lphi[kd] + p.beta4 * 0.25 * d2psi_b(p, v[1][1]) * lm -
+    dphi0[kd] = (double)w.lphi[kd] + p.beta4 * 0.25 * d2psi_b<double>(p, v[1][1]) * lm -
                 p.kappa * lap_T(p, w.lmu_tot, x, y);
-    th[0] = -lap_fwd(v) * lm;
-    th[1] = dpsi_b(p, v[1][1]) * lm;
+    th[0] = -lap_fwd<double>(v) * lm;
+    th[1] = dpsi_b<double>(p, v[1][1]) * lm;
   }
   block_sum_add<2>(th, th_part + (long long)tile * NTH + 0);
 }

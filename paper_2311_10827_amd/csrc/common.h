@@ -82,9 +82,11 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
 }
 
 // Stencil neighbour: periodic wrap, or the mirrored adjacent cell across a
-// wall.  Valid for any integer v.
+// wall.  Valid for any integer v; one period out of range costs a compare,
+// the general remainder runs only for lanes farther out.
 __device__ __forceinline__ int stencil_idx(int v, int n, int wall) {
   if (wall) return v < 0 ? 0 : (v >= n ? n - 1 : v);
+  if (v >= -n && v < 2 * n) return v < 0 ? v + n : (v >= n ? v - n : v);
   int r = v % n;
   return r < 0 ? r + n : r;
 }
@@ -110,29 +112,31 @@ struct Pops {
 };
 
 // WITH_G: also gather g.  WITH_F: gather f (and the low word of f_0).
+// Offsets within a plane fit in 32 bits (pitch * ny <= INT32_MAX); the
+// plane of each load is one of two wave-uniform bases (the direction's own
+// or, for a bounce-back lane, the opposite one).
 template <bool WITH_G, typename T, bool WITH_F = true>
 __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int x, int y, Pops<T>& q) {
   const PullCols px = pull_cols(x, p.nx, p.bcx);
   const PullCols py = pull_cols(y, p.ny, p.bcy);
-  const long long own = (long long)y * p.pitch + x;
+  const unsigned own = (unsigned)(y * p.pitch + x);
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const int cx = cx_of(i), cy = cy_of(i);
     const int sx = cx == 1 ? px.m : (cx == -1 ? px.p : x);
     const int sy = cy == 1 ? py.m : (cy == -1 ? py.p : y);
-    long long off;
-    int plane;
-    if (sx < 0 || sy < 0) {
-      plane = opp_of(i);
-      off = own;
-    } else {
-      plane = i;
-      off = (long long)sy * p.pitch + sx;
+    const bool bb = sx < 0 || sy < 0;
+    const unsigned off = bb ? own : (unsigned)(sy * p.pitch + sx);
+    if (WITH_F) {
+      const T* pf = bb ? B + opp_of(i) * p.ps : B + i * p.ps;
+      q.f[i] = pf[off];
     }
-    if (WITH_F) q.f[i] = B[plane * p.ps + off];
-    if (WITH_G) q.g[i] = B[(9 + plane) * p.ps + off];
+    if (WITH_G) {
+      const T* pg = bb ? B + (9 + opp_of(i)) * p.ps : B + (9 + i) * p.ps;
+      q.g[i] = pg[off];
+    }
   }
-  if (WITH_F && std::is_same<T, float>::value) q.lo = B[LO_PLANE * p.ps + own];
+  if (WITH_F && std::is_same<T, float>::value) q.lo = (B + LO_PLANE * p.ps)[own];
 }
 
 // Store one pre-collision population so that the pull gather returns it:

@@ -176,11 +176,11 @@ __device__ __forceinline__ void load_nbhd(const KP& p, const T* __restrict__ dph
   const int ys[3] = {stencil_idx(y - 1, p.ny, p.bcy), y, stencil_idx(y + 1, p.ny, p.bcy)};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const long long r = (long long)ys[a] * p.pitch;
+    const unsigned r = (unsigned)(ys[a] * p.pitch);
 #pragma unroll
     for (int b = 0; b < 3; ++b) {
-      n.ph[a][b] = dphi[r + xs[b]];
-      n.mu[a][b] = mupl[r + xs[b]];
+      n.ph[a][b] = dphi[r + (unsigned)xs[b]];
+      n.mu[a][b] = mupl[r + (unsigned)xs[b]];
     }
   }
 }
@@ -339,7 +339,7 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
   Diag dg;
   if (DIAG) diag_identity(dg);
   if (valid) {
-    const long long o = (long long)y * p.pitch + x;
+    const unsigned o = (unsigned)(y * p.pitch + x);
     Pops<T> q;
     gather<true>(Bin, p, x, y, q);
     Nbhd<T> nb;
@@ -355,10 +355,10 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
     if (WRITE) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        Bout[i * p.ps + o] = fo[i];
-        Bout[(9 + i) * p.ps + o] = go[i];
+        (Bout + i * p.ps)[o] = fo[i];
+        (Bout + (9 + i) * p.ps)[o] = go[i];
       }
-      if constexpr (std::is_same<T, float>::value) Bout[LO_PLANE * p.ps + o] = lo;
+      if constexpr (std::is_same<T, float>::value) (Bout + LO_PLANE * p.ps)[o] = lo;
       Spout[o] = (T)c.S;
     }
     if (MODE == M_INIT_S) Spout[o] = (T)c.S;
@@ -394,33 +394,43 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
 constexpr int RED_BLOCKS = 1024;
 // ------------------------------------------- fused step: phi, mu, collide
 // One workgroup owns a strip of W columns and H rows and marches up it.
-// Per row y it gathers f at row y+2 for phi (5-row ring in LDS, W + 4
-// columns) and keeps the strip's own gathered f (4-row ring), computes mu of
-// row y+1 (3-row ring, W + 2 columns) and then collides row y with the same
-// arithmetic as k_collide: f and the 3x3 phi and mu come from LDS, only g is
-// gathered from memory.  Every population plane is read from HBM once (up
-// to the ring recompute at strip edges); phi and mu never go to HBM unless
-// WRITE_PHIMU asks for them (the adjoint's recompute keeps them).  Same
-// results as k_phi_mu + k_collide, bit for bit.
+// Per row y it takes the f gathered at row y+2 to phi (5-row ring in LDS,
+// W + 4 columns) and keeps the strip's own gathered f (FR-row ring),
+// computes mu of row y+1 (3-row ring, W + 2 columns) and then collides row y
+// with the same arithmetic as k_collide: f and the 3x3 phi and mu come from
+// LDS, only g is gathered from memory.  Every population plane is read from
+// HBM once (up to the ring recompute at strip edges); phi and mu never go to
+// HBM unless WRITE_PHIMU asks for them (the adjoint's recompute keeps them).
+// Same results as k_phi_mu + k_collide, bit for bit.
+//
+// The row loop is software-pipelined: the loads of the next row (f for phi
+// of row y+3, g and S_prev of row y+1) are issued after row y's collision
+// and before its stores.  Vector memory operations of a wave complete in
+// issue order, so the wait for those loads at the top of the next iteration
+// does not include this row's stores, and the loads are in flight across
+// the stores, the ring updates and the barriers.
 //
 // Ghosts: ring entries outside the grid hold phi of the wrapped or mirrored
 // cell; a mu entry just outside a wall holds mu of the adjacent cell (its
 // stencil is shifted by one), which is what the two-kernel path reads
 // through stencil_idx.
-// Strip width (= threads per workgroup) and height.
+//
+// Strip width W (= threads per workgroup) and the largest strip height H;
+// the host lowers the height (a kernel argument) on small grids so that a
+// launch has more workgroups.
 template <typename T>
 struct Strip;
-// KEEP_F: keep the strip's gathered f in LDS for the collision (FP32);
-// FP64 re-gathers f instead, since the FP64 ring would leave room for one
-// workgroup per CU.
+// KEEP_F: keep the strip's gathered f in LDS for the collision (FP32), in a
+// ring of FR rows; FP64 re-gathers f instead, since the FP64 ring would
+// leave room for one workgroup per CU.
 template <>
 struct Strip<float> {
-  static constexpr int W = 256, H = 64;
+  static constexpr int W = 256, H = 64, FR = 4;
   static constexpr bool KEEP_F = true;
 };
 template <>
 struct Strip<double> {
-  static constexpr int W = 256, H = 64;
+  static constexpr int W = 256, H = 64, FR = 1;
   static constexpr bool KEEP_F = false;
 };
 
@@ -433,41 +443,50 @@ template <typename T, int MODE, bool WRITE_PHIMU>
 __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T* Bin, T* Bout, const T* Spin,
                                                              T* Spout, T* __restrict__ dphi_out,
                                                              T* __restrict__ mu_out,
-                                                             double* __restrict__ partials, int ntx) {
+                                                             double* __restrict__ partials, int ntx,
+                                                             int H) {
   constexpr bool DIAG = MODE == M_STEP_DIAG;
-  constexpr int W = Strip<T>::W, H = Strip<T>::H;
+  constexpr int W = Strip<T>::W;
   constexpr bool KEEP_F = Strip<T>::KEEP_F;
+  constexpr int FR = KEEP_F ? Strip<T>::FR : 1;
+  static_assert(FR == 1 || FR == 3 || FR == 4, "f ring of 3 or 4 rows");
   constexpr int NF = std::is_same<T, float>::value ? 10 : 9;  // f_0..f_8 (+ low word of f_0)
-  __shared__ T phr[5][W + 4];                  // phi - phi_ref, column x0 - 2 + k
-  __shared__ T mur[3][W + 2];                  // mu, column x0 - 1 + k
-  __shared__ T fr[KEEP_F ? 4 : 1][NF][W];      // gathered f of the strip's own columns
+  __shared__ T phr[5][W + 4];     // phi - phi_ref, column x0 - 2 + k
+  __shared__ T mur[3][W + 2];     // mu, column x0 - 1 + k
+  __shared__ T fr[FR][NF][W];     // gathered f of the strip's own columns
   const int blk = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (blk % ntx) * W, y0 = (blk / ntx) * H;
   const int y1 = y0 + H < p.ny ? y0 + H : p.ny;
   const int t = threadIdx.x;
 
-  // phi of row yu (unwrapped) on W + 4 columns; for rows this strip collides
-  // the gathered f of its own columns is kept for the collision.
-  auto phi_row = [&](int yu) {
+  // f of the phi columns a thread owns in one row: k = t and, for t < 4,
+  // k = W + t.
+  struct PhiCols {
+    Pops<T> a, b;
+  };
+  auto phi_load = [&](int yu, PhiCols& L) {
     const int gy = stencil_idx(yu, p.ny, p.bcy);
-    T* row = phr[mod_pos(yu, 5)];
-    const bool keep = yu >= y0 && yu < y1;
-    T(*fk)[W] = fr[KEEP_F ? mod_pos(yu, 4) : 0];
-    for (int k = t; k < W + 4; k += W) {
-      const int gx = stencil_idx(x0 - 2 + k, p.nx, p.bcx);
-      Pops<T> q;
-      gather<false>(Bin, p, gx, gy, q);
-      const T v = phi_sum<T>(q);
-      row[k] = v;
-      if (keep && k >= 2 && k < W + 2) {
-        if constexpr (KEEP_F) {
+    gather<false>(Bin, p, stencil_idx(x0 - 2 + t, p.nx, p.bcx), gy, L.a);
+    if (t < 4) gather<false>(Bin, p, stencil_idx(x0 - 2 + W + t, p.nx, p.bcx), gy, L.b);
+  };
+  // phi of row yu (unwrapped) into the ring; for rows this strip collides
+  // the gathered f of its own columns is kept for the collision.
+  auto phi_put = [&](int yu, const Pops<T>& q, int k) {
+    const T v = phi_sum<T>(q);
+    phr[mod_pos(yu, 5)][k] = v;
+    if (yu >= y0 && yu < y1 && k >= 2 && k < W + 2) {
+      if constexpr (KEEP_F) {
+        T(*fk)[W] = fr[mod_pos(yu, FR)];
 #pragma unroll
-          for (int i = 0; i < 9; ++i) fk[i][k - 2] = q.f[i];
-          if constexpr (NF == 10) fk[9][k - 2] = q.lo;
-        }
-        if (WRITE_PHIMU && x0 - 2 + k < p.nx) dphi_out[(long long)yu * p.pitch + (x0 - 2 + k)] = v;
+        for (int i = 0; i < 9; ++i) fk[i][k - 2] = q.f[i];
+        if constexpr (NF == 10) fk[9][k - 2] = q.lo;
       }
+      if (WRITE_PHIMU && x0 - 2 + k < p.nx) dphi_out[(long long)yu * p.pitch + (x0 - 2 + k)] = v;
     }
+  };
+  auto phi_store = [&](int yu, const PhiCols& L) {
+    phi_put(yu, L.a, t);
+    if (t < 4) phi_put(yu, L.b, W + t);
   };
   auto mu_row = [&](int yu) {
     // stencil rows shifted inward for a ghost row beyond a wall
@@ -488,41 +507,47 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
         mu_out[(long long)yu * p.pitch + xu] = m;
     }
   };
+  const int x = x0 + t;
+  const bool active = x < p.nx;
+  // g and S_prev of row y (and its f without the ring)
+  auto row_load = [&](int y, Pops<T>& q, T& Sp) {
+    gather<true, T, !KEEP_F>(Bin, p, x, y, q);
+    Sp = Spin[(unsigned)(y * p.pitch + x)];
+  };
 
   Diag dg;
   if (DIAG) diag_identity(dg);
-  for (int r = y0 - 2; r <= y0 + 1; ++r) phi_row(r);
+  for (int r = y0 - 2; r <= y0 + 1; ++r) {
+    PhiCols L;
+    phi_load(r, L);
+    phi_store(r, L);
+  }
   __syncthreads();
   mu_row(y0 - 1);
   mu_row(y0);
-  const int x = x0 + t;
-  // Ring hazards: phi_row(y+2) overwrites the phi slot of row y-3 and the f
-  // slot of row y-2, whose last readers (mu_row(y-2), the collision of row
-  // y-2) finished before the barriers of iteration y-1; mu_row(y+1)
+  PhiCols L;
+  Pops<T> q;
+  T Sp = T(0);
+  phi_load(y0 + 2, L);
+  if (active) row_load(y0, q, Sp);
+  // Ring hazards: phi_store(y+2) overwrites the phi slot of row y-3, read
+  // last by mu_row(y-2) and the collision of row y-2, and the f slot of row
+  // y-2 (FR = 4; the collision of row y-2 read it) or of row y-1 (FR = 3;
+  // the collision of row y-1, hence the extra barrier); mu_row(y+1)
   // overwrites the slot of row y-2, read last by the collision of row y-1,
   // which finished before the first barrier of iteration y.
   for (int y = y0; y < y1; ++y) {
-    // Without the f ring (FP64) this row's f, g and S_prev loads are issued
-    // first, so they are in flight across the phi/mu work and the barriers;
-    // with it (FP32) they are issued after the barriers, where the smaller
-    // register footprint keeps more waves resident.
-    const bool active = x < p.nx;
-    const long long o = (long long)y * p.pitch + x;
-    Pops<T> q;
-    T Sp = T(0);
-    if (!KEEP_F && active) {
-      gather<true, T, true>(Bin, p, x, y, q);
-      Sp = Spin[o];
-    }
-    phi_row(y + 2);
+    if (FR == 3) __syncthreads();
+    phi_store(y + 2, L);
     __syncthreads();
     mu_row(y + 1);
     __syncthreads();
+    T fo[9], go[9];
+    T lo = 0;
+    CellOut c;
     if (active) {
       if constexpr (KEEP_F) {
-        gather<true, T, false>(Bin, p, x, y, q);  // g from memory, f from LDS
-        Sp = Spin[o];
-        T(*fk)[W] = fr[mod_pos(y, 4)];
+        T(*fk)[W] = fr[mod_pos(y, FR)];
 #pragma unroll
         for (int i = 0; i < 9; ++i) q.f[i] = fk[i][t];
         if constexpr (NF == 10) q.lo = fk[9][t];
@@ -538,14 +563,19 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
           nb.mu[a][b] = mr[t + b];
         }
       }
-      T fo[9], go[9];
-      T lo = 0;
-      CellOut c;
       if constexpr (std::is_same<T, double>::value)
         cell_f64<true>(p, q, nb, Sp, fo, go, c);
       else
         cell_f32<true>(p, q, nb, Sp, fo, lo, go, c);
+    }
+    // next row's loads go out before this row's stores
+    if (y + 1 < y1) {
+      phi_load(y + 3, L);
+      if (active) row_load(y + 1, q, Sp);
+    }
+    if (active) {
       // streaming stores: nothing reads them before they leave the caches
+      const unsigned o = (unsigned)(y * p.pitch + x);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
         __builtin_nontemporal_store(fo[i], Bout + i * p.ps + o);

@@ -35,7 +35,9 @@ struct lbm_ctx {
   int cur;
   int64_t step;
   int ntx1, nty1, ntx2, nty2;
-  int ntxf, ntyf;       // strips of the fused step kernel
+  int ntxf, ntyf, hf;   // strips of the fused step kernel and their height
+  int ntxm, ntym;       // tiles of ka_mu_phi (no more than the K2 tiles, whose
+                        // count sizes the parameter partials)
   bool fused;           // lbm_step runs the fused kernel (kernel_path 0)
   double* partials;
   double* red_mid;      // [RED_BLOCKS][NQ]: first-level reduction results
@@ -109,6 +111,8 @@ struct Layout {
 };
 
 constexpr int ADJ_PLANES = 7;
+// fused step launches aim at no fewer workgroups than this (8 per CU)
+constexpr long long FUSED_MIN_BLOCKS = 2048;
 
 size_t adj_plane_bytes(const lbm_params* p) {
   return round_up((size_t)p->nx * p->ny * (p->precision == 32 ? 4 : 8), 256);
@@ -196,7 +200,7 @@ int launch_collide(lbm_ctx* c, MomOut mo) {
 template <typename T, int MODE, bool WRITE_PHIMU>
 int launch_fused(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
   hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU>), dim3(c->ntxf * c->ntyf), dim3(Strip<T>::W), 0,
-                     c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf);
+                     c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf, c->hf);
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -401,8 +405,8 @@ int adjoint_step_impl(lbm_ctx* c, T* state, const T* lam_in, T* lam_out, bool ha
   hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state,
                      snap_S(c, state), dphi, mu, lam_in, lam_out, w, c->th_part, c->ntx2);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi, lam_in, lam_out,
-                     w, c->th_part, c->ntx2);
+  hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(c->ntxm * c->ntym), dim3(256), 0, c->stream, c->kp, dphi,
+                     lam_in, lam_out, w, c->th_part, c->ntxm);
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -441,8 +445,8 @@ int adjoint_init_impl(lbm_ctx* c, const T* state, const double* phi0, const T* l
                      snap_S(c, state), dphi_plane<T>(c), mu_plane<T>(c), lam0, scratch, w, c->th_part,
                      c->ntx2);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL((ka_mu_phi<T, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, dphi_plane<T>(c), lam0,
-                     scratch, w, c->th_part, c->ntx2);
+  hipLaunchKernelGGL((ka_mu_phi<T, true>), dim3(c->ntxm * c->ntym), dim3(256), 0, c->stream, c->kp,
+                     dphi_plane<T>(c), lam0, scratch, w, c->th_part, c->ntxm);
   LAUNCHCHK(c);
   // mu0 = mu(phi0) into the mu plane
   hipLaunchKernelGGL((k_phi_mu<T, true>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, nullptr,
@@ -503,11 +507,18 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   c->ntx2 = L.ntx2;
   c->nty2 = L.nty2;
   {
+    // Strip height: the full height, halved (down to 8 rows; each strip
+    // recomputes phi on 4 rows beyond its own) while the launch has fewer
+    // than FUSED_MIN_BLOCKS workgroups.
     const int sw = p->precision == 32 ? Strip<float>::W : Strip<double>::W;
-    const int sh = p->precision == 32 ? Strip<float>::H : Strip<double>::H;
+    int sh = p->precision == 32 ? Strip<float>::H : Strip<double>::H;
     c->ntxf = (p->nx + sw - 1) / sw;
+    while (sh > 8 && (long long)c->ntxf * ((p->ny + sh - 1) / sh) < FUSED_MIN_BLOCKS) sh /= 2;
+    c->hf = sh;
     c->ntyf = (p->ny + sh - 1) / sh;
   }
+  c->ntxm = (p->nx + KM_TX - 1) / KM_TX;
+  c->ntym = (p->ny + KM_TY - 1) / KM_TY;
   c->fused = p->kernel_path == 0;
   c->partials = reinterpret_cast<double*>(c->ws);
   c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
