@@ -81,6 +81,20 @@ __device__ __forceinline__ int xcd_tile(int b, int n) {
   return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
 }
 
+// A wave-uniform pointer (a plane base) as a global-memory pointer, passed
+// through readfirstlane so that it stays in scalar registers: the compiler
+// may then not fold a lane's offset into it, and each access is the base
+// plus one vector offset.
+template <typename P>
+using gmem = __attribute__((address_space(1))) P*;
+template <typename P>
+__device__ __forceinline__ gmem<P> uni(P* ptr) {
+  const unsigned long long v = reinterpret_cast<unsigned long long>(ptr);
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return (gmem<P>)(((unsigned long long)hi << 32) | lo);
+}
+
 // Stencil neighbour: periodic wrap, or the mirrored adjacent cell across a
 // wall.  Valid for any integer v; one period out of range costs a compare,
 // the general remainder runs only for lanes farther out.

@@ -402,11 +402,11 @@ int adjoint_step_impl(lbm_ctx* c, T* state, const T* lam_in, T* lam_out, bool ha
   }
   const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
   const AdjWork<T> w = adj_work<T>(c);
-  hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state,
-                     snap_S(c, state), dphi, mu, lam_in, lam_out, w, c->th_part, c->ntx2);
+  hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu, lam_in,
+                     lam_out, w, c->th_part, c->ntx2);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(c->ntxm * c->ntym), dim3(256), 0, c->stream, c->kp, dphi,
-                     lam_in, lam_out, w, c->th_part, c->ntxm);
+  hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(c->ntxm * c->ntym), dim3(KM_THREADS), 0, c->stream, c->kp,
+                     dphi, lam_in, lam_out, w, c->th_part, c->ntxm);
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -441,11 +441,10 @@ int adjoint_init_impl(lbm_ctx* c, const T* state, const double* phi0, const T* l
   if (r) return r;
   const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
   const AdjWork<T> w = adj_work<T>(c);
-  hipLaunchKernelGGL((ka_local<T, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state,
-                     snap_S(c, state), dphi_plane<T>(c), mu_plane<T>(c), lam0, scratch, w, c->th_part,
-                     c->ntx2);
+  hipLaunchKernelGGL((ka_local<T, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi_plane<T>(c),
+                     mu_plane<T>(c), lam0, scratch, w, c->th_part, c->ntx2);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL((ka_mu_phi<T, true>), dim3(c->ntxm * c->ntym), dim3(256), 0, c->stream, c->kp,
+  hipLaunchKernelGGL((ka_mu_phi<T, true>), dim3(c->ntxm * c->ntym), dim3(KM_THREADS), 0, c->stream, c->kp,
                      dphi_plane<T>(c), lam0, scratch, w, c->th_part, c->ntxm);
   LAUNCHCHK(c);
   // mu0 = mu(phi0) into the mu plane
