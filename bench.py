@@ -34,7 +34,7 @@ STEP_BYTES = {32: (19 + 19 + 1 + 1) * 4, 64: (18 + 18 + 1 + 1) * 8}
 # The two-kernel path also writes phi and mu and reads them back, and reads
 # the f planes twice: +(2 + 2 + 10) * 4 B in FP32, +(2 + 2 + 9) * 8 B in FP64.
 TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (2 + 2 + 10) * 4, 64: STEP_BYTES[64] + (2 + 2 + 9) * 8}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_collide_many_drops_16384.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fused_many_drops_16384.json")
 
 
 def log(*a):
@@ -51,18 +51,19 @@ def kernel_source_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec: int):
-    """HBM bytes per launch of the collide kernel from the committed rocprofv3
+def measured_traffic(key: str):
+    """HBM bytes per launch of the fused step kernel ("32", "64"), or per step
+    of the two-kernel path ("two_kernel_32"), from the committed rocprofv3
     counter summary, if it was taken on the current kernel source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    rec = t.get(str(prec))
+    rec = t.get(key)
     if not rec or t.get("source_sha256_16") != kernel_source_hash():
         return None
-    return rec.get("bytes_per_launch")
+    return rec.get("bytes_per_launch", rec.get("bytes_per_step"))
 
 
 def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl, kernel_path: int = 0):
@@ -101,6 +102,7 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
     avg = kms / n
     alg = STEP_BYTES[prec] if kernel_path == 0 else TWO_KERNEL_BYTES[prec]
     ach = alg * ncell / (avg * 1e-3) / 1e9
+    traffic = measured_traffic(str(prec) if kernel_path == 0 else f"two_kernel_{prec}")
     return {
         "mlups": ncell * steps / (ms * 1e-3) / 1e6,
         "ms_per_step": ms / steps,
@@ -112,8 +114,12 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
             "peak": HBM_PEAK_GBPS,
             "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBPS, 4),
-            "traffic": measured_traffic(prec) if kernel_path == 0 else None,
+            "traffic": traffic,
         },
+        # the counted HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
+        # over the same live kernel time
+        "measured_bytes_frac": None if traffic is None
+        else round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "diag_after": {k: d[k] for k in ("sum_phi", "max_u", "min_rho", "n_nonfinite", "step")},
     }
 
@@ -293,6 +299,7 @@ def main():
             "parallelism": "single GPU",
         },
         "roofline": r32["roofline"],
+        "measured_bytes_frac": r32["measured_bytes_frac"],
         "cpu_baseline": cpu,
         "kernel_ms": round(r32["kernel_ms"], 4),
         "algorithmic_bytes_per_cell": STEP_BYTES[32],
@@ -300,11 +307,12 @@ def main():
         "fp64": None if r64 is None else {
             "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 4),
             "kernel_ms": round(r64["kernel_ms"], 4), "algorithmic_bytes_per_cell": STEP_BYTES[64],
-            "roofline": r64["roofline"],
+            "roofline": r64["roofline"], "measured_bytes_frac": r64["measured_bytes_frac"],
         },
         "two_kernel_fp32": None if r2k is None else {
             "value": round(r2k["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r2k["ms_per_step"], 4),
             "algorithmic_bytes_per_cell": TWO_KERNEL_BYTES[32], "roofline": r2k["roofline"],
+            "measured_bytes_frac": r2k["measured_bytes_frac"],
         },
         "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],

@@ -420,18 +420,16 @@ constexpr int RED_BLOCKS = 1024;
 // launch has more workgroups.
 template <typename T>
 struct Strip;
-// KEEP_F: keep the strip's gathered f in LDS for the collision (FP32), in a
-// ring of FR rows; FP64 re-gathers f instead, since the FP64 ring would
-// leave room for one workgroup per CU.
+// FR: rows in the LDS ring of the strip's gathered f.  Four rows (FP32, 40
+// KiB) need no barrier beyond the two per row; three rows (FP64, 54 KiB, so
+// that two workgroups fit a CU) need one more per row.
 template <>
 struct Strip<float> {
   static constexpr int W = 256, H = 64, FR = 4;
-  static constexpr bool KEEP_F = true;
 };
 template <>
 struct Strip<double> {
-  static constexpr int W = 256, H = 64, FR = 1;
-  static constexpr bool KEEP_F = false;
+  static constexpr int W = 256, H = 64, FR = 3;
 };
 
 __device__ __forceinline__ int mod_pos(int a, int m) {
@@ -447,9 +445,8 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
                                                              int H) {
   constexpr bool DIAG = MODE == M_STEP_DIAG;
   constexpr int W = Strip<T>::W;
-  constexpr bool KEEP_F = Strip<T>::KEEP_F;
-  constexpr int FR = KEEP_F ? Strip<T>::FR : 1;
-  static_assert(FR == 1 || FR == 3 || FR == 4, "f ring of 3 or 4 rows");
+  constexpr int FR = Strip<T>::FR;
+  static_assert(FR == 3 || FR == 4, "f ring of 3 or 4 rows");
   constexpr int NF = std::is_same<T, float>::value ? 10 : 9;  // f_0..f_8 (+ low word of f_0)
   __shared__ T phr[5][W + 4];     // phi - phi_ref, column x0 - 2 + k
   __shared__ T mur[3][W + 2];     // mu, column x0 - 1 + k
@@ -475,12 +472,10 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
     const T v = phi_sum<T>(q);
     phr[mod_pos(yu, 5)][k] = v;
     if (yu >= y0 && yu < y1 && k >= 2 && k < W + 2) {
-      if constexpr (KEEP_F) {
-        T(*fk)[W] = fr[mod_pos(yu, FR)];
+      T(*fk)[W] = fr[mod_pos(yu, FR)];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) fk[i][k - 2] = q.f[i];
-        if constexpr (NF == 10) fk[9][k - 2] = q.lo;
-      }
+      for (int i = 0; i < 9; ++i) fk[i][k - 2] = q.f[i];
+      if constexpr (NF == 10) fk[9][k - 2] = q.lo;
       if (WRITE_PHIMU && x0 - 2 + k < p.nx) dphi_out[(long long)yu * p.pitch + (x0 - 2 + k)] = v;
     }
   };
@@ -509,9 +504,9 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
   };
   const int x = x0 + t;
   const bool active = x < p.nx;
-  // g and S_prev of row y (and its f without the ring)
+  // g and S_prev of row y (its f is in the ring)
   auto row_load = [&](int y, Pops<T>& q, T& Sp) {
-    gather<true, T, !KEEP_F>(Bin, p, x, y, q);
+    gather<true, T, false>(Bin, p, x, y, q);
     Sp = Spin[(unsigned)(y * p.pitch + x)];
   };
 
@@ -546,12 +541,10 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
     T lo = 0;
     CellOut c;
     if (active) {
-      if constexpr (KEEP_F) {
-        T(*fk)[W] = fr[mod_pos(y, FR)];
+      T(*fk)[W] = fr[mod_pos(y, FR)];
 #pragma unroll
-        for (int i = 0; i < 9; ++i) q.f[i] = fk[i][t];
-        if constexpr (NF == 10) q.lo = fk[9][t];
-      }
+      for (int i = 0; i < 9; ++i) q.f[i] = fk[i][t];
+      if constexpr (NF == 10) q.lo = fk[9][t];
       Nbhd<T> nb;
 #pragma unroll
       for (int a = 0; a < 3; ++a) {
