@@ -319,6 +319,27 @@ def test_fused_and_two_kernel_paths_agree_bitwise(prec, name):
     assert da["sum_phi"] == pytest.approx(db["sum_phi"], rel=1e-13, abs=1e-13)
 
 
+@pytest.mark.parametrize("prec", [64, 32])
+@pytest.mark.parametrize("shape,bc", [((4100, 2050), 0), ((8200, 2100), 1)])
+def test_fused_and_two_kernel_paths_agree_bitwise_large(prec, shape, bc):
+    # Grids large enough that the fused kernel runs strips 16 (4100 x 2050)
+    # and 32 (8200 x 2100) rows high, with ragged last strips in x and y; the
+    # states are compared on the device.
+    nx, ny = shape
+    wl = inputs.COALESCENCE
+    phi0 = inputs.two_drops(nx, ny, 0.2 * ny, 5.0, noise=1e-3)
+    say(f"[gpu] fused vs two-kernel {nx}x{ny} walls={bc} prec={prec}")
+    over = dict(nx=nx, ny=ny, bc_x=bc, bc_y=bc)
+    a = gpu_sim(wl, phi0, prec, kernel_path=0, **over).step(6)
+    sa = a.get_state()
+    a.close()
+    b = gpu_sim(wl, phi0, prec, kernel_path=1, **over).step(6)
+    sb = b.get_state()
+    b.close()
+    for x, y in zip(sa, sb):
+        assert torch.equal(x, y)
+
+
 def test_fused_step_into_writes_phi_mu_for_the_adjoint():
     # lbm_step_into leaves phi and mu of its source in the snapshot; the
     # adjoint with and without that shortcut gives the same lambda.
