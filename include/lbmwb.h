@@ -77,9 +77,12 @@ enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
  *                      from the rest equilibrium; diagnostics stay FP64.
  *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
  *                  diagnostic pass every k steps (see lbm_step).
- *   kernel_path    0: one fused kernel per step (phi and mu kept on chip);
+ *   kernel_path    0: automatic: the fused kernel when the grid gives its
+ *                  launch enough workgroups (at least 1024 strips of 256 x
+ *                  8 cells in FP32, 512 in FP64), else the two kernels;
  *                  1: the phi/mu pass and the collide-stream pass as two
- *                  kernels.  Both give the same results bit for bit.
+ *                  kernels; 2: one fused kernel per step (phi and mu kept
+ *                  on chip).  All give the same results bit for bit.
  */
 typedef struct lbm_params {
   int32_t nx, ny;

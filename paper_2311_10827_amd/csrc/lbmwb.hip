@@ -38,7 +38,7 @@ struct lbm_ctx {
   int ntxf, ntyf, hf;   // strips of the fused step kernel and their height
   int ntxm, ntym;       // tiles of ka_mu_phi (no more than the K2 tiles, whose
                         // count sizes the parameter partials)
-  bool fused;           // lbm_step runs the fused kernel (kernel_path 0)
+  bool fused;           // lbm_step runs the fused kernel
   double* partials;
   double* red_mid;      // [RED_BLOCKS][NQ]: first-level reduction results
   double* diag_dev;     // [2][NQ]: fused step diagnostics, moments diagnostics
@@ -66,7 +66,7 @@ int validate(const lbm_params* p, lbm_derived* d) {
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return LBM_EINVAL;
   if (p->precision != 32 && p->precision != 64) return LBM_EINVAL;
   if (p->diag_every < 0) return LBM_EINVAL;
-  if (p->kernel_path != 0 && p->kernel_path != 1) return LBM_EINVAL;
+  if (p->kernel_path < 0 || p->kernel_path > 2) return LBM_EINVAL;
   const size_t pitch = round_up((size_t)p->nx, 64);
   if (pitch * (size_t)p->ny > (size_t)INT32_MAX) return LBM_EINVAL;
   const double dphi = p->phi_A - p->phi_B;
@@ -107,12 +107,15 @@ struct Layout {
   size_t state_bytes, ws_bytes;
   int ntx1, nty1, ntx2, nty2;
   int ntxf, ntyf;       // strips of the fused step kernel
-  bool fused;           // lbm_step runs the fused kernel (kernel_path 0)
+  bool fused;           // lbm_step runs the fused kernel
 };
 
 constexpr int ADJ_PLANES = 7;
 // fused step launches aim at no fewer workgroups than this (8 per CU)
 constexpr long long FUSED_MIN_BLOCKS = 2048;
+// kernel_path 0 runs the fused step when the grid gives at least this many
+// strips of 256 x 8 cells
+constexpr long long FUSED_AUTO_STRIPS_32 = 1024, FUSED_AUTO_STRIPS_64 = 512;
 
 size_t adj_plane_bytes(const lbm_params* p) {
   return round_up((size_t)p->nx * p->ny * (p->precision == 32 ? 4 : 8), 256);
@@ -253,8 +256,8 @@ int consume_diag(lbm_ctx* c, bool wait) {
   return LBM_OK;
 }
 
-// One step.  kernel_path 0: the fused kernel (phi and mu stay in LDS);
-// 1: the phi/mu pass then the collide-stream pass.
+// One step: the fused kernel (phi and mu stay in LDS), or the phi/mu pass
+// then the collide-stream pass.
 template <typename T>
 int launch_step(lbm_ctx* c, bool diag) {
   if (c->fused) {
@@ -518,7 +521,15 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   }
   c->ntxm = (p->nx + KM_TX - 1) / KM_TX;
   c->ntym = (p->ny + KM_TY - 1) / KM_TY;
-  c->fused = p->kernel_path == 0;
+  {
+    // Automatic choice: the fused kernel marches its strips row by row, so
+    // on grids that give it few strips even at the lowest height its serial
+    // rows cost more than the second kernel's HBM round trip of phi and mu
+    // (measured crossover: 1024^2 in FP64, 2048^2 in FP32).
+    const long long strips8 = (long long)c->ntxf * ((p->ny + 7) / 8);
+    const long long need = p->precision == 32 ? FUSED_AUTO_STRIPS_32 : FUSED_AUTO_STRIPS_64;
+    c->fused = p->kernel_path == 2 || (p->kernel_path == 0 && strips8 >= need);
+  }
   c->partials = reinterpret_cast<double*>(c->ws);
   c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
   c->diag_dev = c->red_mid + (size_t)RED_BLOCKS * NQ;

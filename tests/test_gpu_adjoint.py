@@ -139,12 +139,13 @@ def test_dot_product_multistep_recompute():
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300)
 
 
+@pytest.mark.parametrize("path", [1, 2])
 @pytest.mark.parametrize("prec", [64, 32])
-def test_step_into_equals_step_bitwise(prec):
+def test_step_into_equals_step_bitwise(prec, path):
     wl = inputs.ADJOINT
     phi0 = inputs.two_drops(90, 70, 14.0, 5.0, noise=1e-3)
-    say(f"[gpu] step_into vs step prec={prec}")
-    sim = gpu_sim(wl, phi0, prec, nx=90, ny=70)
+    say(f"[gpu] step_into vs step prec={prec} kernel_path={path}")
+    sim = gpu_sim(wl, phi0, prec, kernel_path=path, nx=90, ny=70)
     s0 = sim.snapshot()
     a, b = sim.new_snapshot(), sim.new_snapshot()
     sim.step_into(s0, a)

@@ -52,11 +52,17 @@ def _case(name):
 CASES = ["flat", "drop64", "ragged_walls", "ragged_periodic", "tiny_periodic", "tiny_walls", "one_column"]
 
 
+# kernel_path 1: phi/mu pass + collide pass; 2: the fused step kernel
+# (0, the default, picks one of them by grid size).
+PATHS = [1, 2]
+
+
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("name", CASES)
-def test_fp64_init_and_steps_match_oracle(name):
+def test_fp64_init_and_steps_match_oracle(name, path):
     wl, phi0, over = _case(name)
-    say(f"[gpu] fp64 parity {name} shape={phi0.shape}")
-    g = gpu_sim(wl, phi0, 64, **over)
+    say(f"[gpu] fp64 parity {name} shape={phi0.shape} kernel_path={path}")
+    g = gpu_sim(wl, phi0, 64, kernel_path=path, **over)
     o = oracle_sim(wl, phi0, **over)
     done = 0
     for n in (0, 1, 9, 290):
@@ -70,10 +76,11 @@ def test_fp64_init_and_steps_match_oracle(name):
     assert g.step_count == done
 
 
-def test_fp64_flat_interface_long_run():
+@pytest.mark.parametrize("path", PATHS)
+def test_fp64_flat_interface_long_run(path):
     wl, phi0, over = _case("flat")
-    say("[gpu] fp64 flat 256x4 20000 steps")
-    g = gpu_sim(wl, phi0, 64)
+    say(f"[gpu] fp64 flat 256x4 20000 steps kernel_path={path}")
+    g = gpu_sim(wl, phi0, 64, kernel_path=path)
     o = oracle_sim(wl, phi0)
     g.step(20000)
     o.step(20000)
@@ -83,14 +90,15 @@ def test_fp64_flat_interface_long_run():
     assert 1.4e-2 <= np.abs(gm["phi"] - phi0).max() <= 1.7e-2
 
 
-def test_fp64_coalescence_crop():
+@pytest.mark.parametrize("path", PATHS)
+def test_fp64_coalescence_crop(path):
     # 512 x 512 window of the 4096^2 two-drop field with seeded noise.
     wl = inputs.COALESCENCE
     x0, y0, w, h = wl.extra["crop"]
     full = inputs.two_drops(4096, 4096, wl.extra["R"], wl.W, noise=wl.extra["noise"], workload_id=3)
     phi0 = np.ascontiguousarray(full[y0:y0 + h, x0:x0 + w])
-    say(f"[gpu] fp64 coalescence crop {phi0.shape}")
-    g = gpu_sim(wl, phi0, 64, nx=w, ny=h)
+    say(f"[gpu] fp64 coalescence crop {phi0.shape} kernel_path={path}")
+    g = gpu_sim(wl, phi0, 64, kernel_path=path, nx=w, ny=h)
     o = oracle_sim(wl, phi0, nx=w, ny=h)
     g.step(300)
     o.step(300)
@@ -113,12 +121,13 @@ def test_fp64_well_balanced_fixed_point():
     assert np.abs(gm["mu"] - mu0).max() <= 1e-15
 
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("name", ["flat", "drop64"])
-def test_fp32_error_against_fp64_oracle(name):
+def test_fp32_error_against_fp64_oracle(name, path):
     # FP32 storage: phi within 1e-5 and u within 1e-6 of the FP64 oracle.
     wl, phi0, over = _case(name)
-    say(f"[gpu] fp32 vs oracle {name}")
-    g = gpu_sim(wl, phi0, 32, **over)
+    say(f"[gpu] fp32 vs oracle {name} kernel_path={path}")
+    g = gpu_sim(wl, phi0, 32, kernel_path=path, **over)
     o = oracle_sim(wl, phi0, **over)
     for n in (1, 199, 1800, 3000):
         g.step(n)
@@ -307,10 +316,11 @@ def test_full_size_sampled(prec):
 @pytest.mark.parametrize("prec", [64, 32])
 @pytest.mark.parametrize("name", ["flat", "ragged_walls", "ragged_periodic", "tiny_walls", "one_column"])
 def test_fused_and_two_kernel_paths_agree_bitwise(prec, name):
-    # kernel_path 0 (phi and mu in LDS) and 1 (two kernels) give the same bits.
+    # kernel_path 2 (fused: phi and mu in LDS) and 1 (two kernels) give the
+    # same bits.
     wl, phi0, over = _case(name)
     say(f"[gpu] fused vs two-kernel {name} prec={prec}")
-    a = gpu_sim(wl, phi0, prec, kernel_path=0, diag_every=7, **over).step(150)
+    a = gpu_sim(wl, phi0, prec, kernel_path=2, diag_every=7, **over).step(150)
     b = gpu_sim(wl, phi0, prec, kernel_path=1, diag_every=7, **over).step(150)
     for x, y in zip(gpu_state(a), gpu_state(b)):
         assert np.array_equal(x, y)
@@ -330,7 +340,7 @@ def test_fused_and_two_kernel_paths_agree_bitwise_large(prec, shape, bc):
     phi0 = inputs.two_drops(nx, ny, 0.2 * ny, 5.0, noise=1e-3)
     say(f"[gpu] fused vs two-kernel {nx}x{ny} walls={bc} prec={prec}")
     over = dict(nx=nx, ny=ny, bc_x=bc, bc_y=bc)
-    a = gpu_sim(wl, phi0, prec, kernel_path=0, **over).step(6)
+    a = gpu_sim(wl, phi0, prec, kernel_path=2, **over).step(6)
     sa = a.get_state()
     a.close()
     b = gpu_sim(wl, phi0, prec, kernel_path=1, **over).step(6)
@@ -344,7 +354,7 @@ def test_fused_step_into_writes_phi_mu_for_the_adjoint():
     # lbm_step_into leaves phi and mu of its source in the snapshot; the
     # adjoint with and without that shortcut gives the same lambda.
     wl, phi0, over = _case("ragged_walls")
-    g = gpu_sim(wl, phi0, 64, **over)
+    g = gpu_sim(wl, phi0, 64, kernel_path=2, **over)
     g.enable_adjoint()
     s0, s1 = g.snapshot(), g.new_snapshot()
     g.step_into(s0, s1)
