@@ -240,7 +240,9 @@ int lbm_step_into(lbm_ctx* ctx, void* src, void* dst);
  * the previous-step source.  An adjoint lambda has the same layout as
  * lbm_get_state's outputs packed together: 19 dense planes [ny][nx]
  * (f_0..f_8, g_0..g_8, S_prev) in the storage precision (double for
- * precision 64, float for 32), device memory.  Arithmetic is FP64.
+ * precision 64, float for 32), device memory.  The arithmetic is in the
+ * storage precision, like the forward step's; parameter gradients
+ * accumulate in FP64.
  *
  * Parameter gradients accumulate in the adjoint workspace for
  * theta = (kappa, beta, alpha, tau_f, nu_A, nu_B), each taken as independent

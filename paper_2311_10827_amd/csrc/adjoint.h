@@ -22,8 +22,8 @@
 //       + lambda_phi (phi = sum_i f_i); kappa and beta partials.
 // Transposed stencils enumerate, for each direction, the cells whose
 // neighbour (periodic wrap or wall mirror) is the target cell, so walls get
-// the exact transpose.  Arithmetic is FP64; lambda planes are stored in the
-// state's precision.
+// the exact transpose.  Arithmetic and lambda planes are in the state's
+// precision (as in the forward step); parameter partials are FP64.
 #pragma once
 #include "forward.h"
 

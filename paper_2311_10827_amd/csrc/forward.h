@@ -1,6 +1,8 @@
 // Forward kernels of one time step of the well-balanced phase-field LBM
-// (Ju et al., arXiv 2311.10827): the phi/mu stencil pass (K1) and the fused
-// collide-and-pull-stream pass (K2), plus initialisation and state I/O.
+// (Ju et al., arXiv 2311.10827): the step as one kernel (k_step_fused: phi,
+// mu and the collide-and-pull-stream of a marching strip, phi and mu kept in
+// LDS) or as two (k_phi_mu, the phi/mu stencil pass K1, then k_collide, the
+// collide-and-pull-stream pass K2), plus initialisation and state I/O.
 //
 // FP64 arithmetic is written term by term in the order of the plain
 // definitions (sums over the velocity set in index order, no fused

@@ -1,6 +1,7 @@
 // C ABI of liblbmwb (declared in include/lbmwb.h): parameter validation,
 // memory layout and kernel launches for the well-balanced phase-field LBM
-// step of Ju et al. (arXiv 2311.10827).  The kernels are in forward.h.
+// step of Ju et al. (arXiv 2311.10827).  The kernels are in forward.h (the
+// step) and adjoint.h (its adjoint).
 //
 // State layout in HBM (planes of the storage type T, each 256-byte aligned):
 //   [pop buffer 0][pop buffer 1][S][dphi][mu]
