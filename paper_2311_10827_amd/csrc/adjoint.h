@@ -424,72 +424,187 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
   __shared__ C mt[LH][LW];
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x0 = (tile % ntx) * KM_TX, y0 = (tile / ntx) * KM_TY;
-  for (int k = threadIdx.x; k < LH * LW; k += blockDim.x) {
-    const int ly = k / LW, lx = k - ly * LW;
-    int gx = x0 + lx - 1, gy = y0 + ly - 1;
-    C v = C(0);
-    const bool outx = gx < 0 || gx >= p.nx, outy = gy < 0 || gy >= p.ny;
-    if (!((outx && p.bcx) || (outy && p.bcy))) {
-      gx = stencil_idx(gx, p.nx, 0);
-      gy = stencil_idx(gy, p.ny, 0);
-      v = w.lmu[(unsigned)(gy * p.nx + gx)] + grad_T<C>(p, w.lgmx, w.lgmy, gx, gy);
+  if (!p.bcx && !p.bcy) {
+    // Periodic grid: every ring entry has one preimage per direction.  All
+    // entries' loads are issued before any is used, so the fill costs one
+    // memory round trip instead of one per entry.
+    constexpr int NE = (LH * LW + KM_THREADS - 1) / KM_THREADS;
+    C lm[NE], gxv[NE][8], gyv[NE][8];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int k = min((int)threadIdx.x + e * KM_THREADS, LH * LW - 1);
+      const int ly = k / LW, lx = k - ly * LW;
+      const int gx = stencil_idx(x0 + lx - 1, p.nx, 0), gy = stencil_idx(y0 + ly - 1, p.ny, 0);
+      lm[e] = w.lmu[(unsigned)(gy * p.nx + gx)];
+#pragma unroll
+      for (int d = 1; d < 9; ++d) {
+        const unsigned kk = (unsigned)(pre1(gy, cy_of(d), p.ny) * p.nx + pre1(gx, cx_of(d), p.nx));
+        gxv[e][d - 1] = cx_of(d) != 0 ? w.lgmx[kk] : C(0);
+        gyv[e][d - 1] = cy_of(d) != 0 ? w.lgmy[kk] : C(0);
+      }
     }
-    mt[ly][lx] = v;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int k = (int)threadIdx.x + e * KM_THREADS;
+      if (k < LH * LW) {
+        // the sum of grad_T, term by term
+        C acc = C(0);
+#pragma unroll
+        for (int d = 1; d < 9; ++d) {
+          const C t = cy_of(d) == 0   ? C(cx_of(d)) * gxv[e][d - 1]
+                      : cx_of(d) == 0 ? C(cy_of(d)) * gyv[e][d - 1]
+                                      : C(cx_of(d)) * gxv[e][d - 1] + C(cy_of(d)) * gyv[e][d - 1];
+          acc += C(INV_CS2 * w_of(d)) * t;
+        }
+        const int ly = k / LW, lx = k - ly * LW;
+        mt[ly][lx] = lm[e] + acc;
+      }
+    }
+  } else {
+    for (int k = threadIdx.x; k < LH * LW; k += blockDim.x) {
+      const int ly = k / LW, lx = k - ly * LW;
+      int gx = x0 + lx - 1, gy = y0 + ly - 1;
+      C v = C(0);
+      const bool outx = gx < 0 || gx >= p.nx, outy = gy < 0 || gy >= p.ny;
+      if (!((outx && p.bcx) || (outy && p.bcy))) {
+        gx = stencil_idx(gx, p.nx, 0);
+        gy = stencil_idx(gy, p.ny, 0);
+        v = w.lmu[(unsigned)(gy * p.nx + gx)] + grad_T<C>(p, w.lgmx, w.lgmy, gx, gy);
+      }
+      mt[ly][lx] = v;
+    }
   }
   __syncthreads();
   const long long n = (long long)p.nx * p.ny;
   const int tx = threadIdx.x & (KM_TX - 1);
   const int x = x0 + tx;
   double th[2] = {0.0, 0.0};  // kappa, beta
-  for (int ty = threadIdx.x / KM_TX; ty < KM_TY; ty += KM_THREADS / KM_TX) {
-    const int y = y0 + ty;
-    if (x >= p.nx || y >= p.ny) continue;
-    const unsigned kd = (unsigned)(y * p.nx + x);
-    const int lx = tx + 1, ly = ty + 1;
-    const C lmt = mt[ly][lx];
-    // L^T lambda_mu_tot from LDS
-    C lt = C(0);
-    if (single_pre(x, p.nx, p.bcx) && single_pre(y, p.ny, p.bcy)) {
+  const C k1 = C(1.0 - p.omega_f);
+  if (!p.bcx && !p.bcy) {
+    // Periodic grid: one preimage per direction everywhere.  The loads of
+    // a thread's next row are issued before the current row's arithmetic
+    // and stores, so consecutive rows overlap their memory latency.
+    struct RowIn {
+      C v[3][3];           // phi - phi_ref around the cell
+      C lphi;
+      C gpx[8], gpy[8];    // lambda_{grad phi} at the preimages (G^T)
+      C a[9];              // lambda_{f*}: the transposed pull of lam_in
+    };
+    auto load_row = [&](int ty, RowIn& in) {
+      // rows and columns beyond the grid (ragged tiles) load a valid cell
+      // and are not stored
+      const int y = min(y0 + ty, p.ny - 1), xc = min(x, p.nx - 1);
+      const int xs[3] = {stencil_idx(xc - 1, p.nx, 0), xc, stencil_idx(xc + 1, p.nx, 0)};
+      const int ys[3] = {stencil_idx(y - 1, p.ny, 0), y, stencil_idx(y + 1, p.ny, 0)};
 #pragma unroll
-      for (int d = 1; d < 9; ++d) lt += C(2.0 * INV_CS2 * w_of(d)) * mt[ly - cy_of(d)][lx - cx_of(d)];
-    } else {
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.v[a][b] = dphi[(unsigned)(ys[a] * p.pitch + xs[b])];
+      const unsigned kd = (unsigned)(y * p.nx + xc);
+      in.lphi = w.lphi[kd];
 #pragma unroll
       for (int d = 1; d < 9; ++d) {
-        int ox[2], oy[2];
-        const int nxo = pre_off(x, cx_of(d), p.nx, p.bcx, ox);
-        const int nyo = pre_off(y, cy_of(d), p.ny, p.bcy, oy);
-        for (int a = 0; a < nyo; ++a)
-          for (int b = 0; b < nxo; ++b) lt += C(2.0 * INV_CS2 * w_of(d)) * mt[ly + oy[a]][lx + ox[b]];
+        const unsigned kk = (unsigned)(pre1(y, cy_of(d), p.ny) * p.nx + pre1(xc, cx_of(d), p.nx));
+        in.gpx[d - 1] = cx_of(d) != 0 ? w.lgpx[kk] : C(0);
+        in.gpy[d - 1] = cy_of(d) != 0 ? w.lgpy[kk] : C(0);
       }
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        in.a[j] = C(0);
+        if (!INIT) {
+          const int qx = pre1(xc, -cx_of(j), p.nx), qy = pre1(y, -cy_of(j), p.ny);
+          in.a[j] = uni(lam_in + j * n)[(unsigned)(qy * p.nx + qx)];
+        }
+      }
+    };
+    auto finish_row = [&](int ty, RowIn& in) {
+      const int y = y0 + ty;
+      if (x >= p.nx || y >= p.ny) return;
+      const unsigned kd = (unsigned)(y * p.nx + x);
+      const int lx = tx + 1, ly = ty + 1;
+      const C lmt = mt[ly][lx];
+      C lt = C(0);
+#pragma unroll
+      for (int d = 1; d < 9; ++d) lt += C(2.0 * INV_CS2 * w_of(d)) * mt[ly - cy_of(d)][lx - cx_of(d)];
+      lt -= C(2.0 * INV_CS2 * (1.0 - w_of(0))) * lmt;
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) in.v[a][b] += C(p.phi_ref);
+      const C ph = in.v[1][1];
+      th[0] += (double)(-lap_fwd<C>(in.v) * lmt);  // mu = psi'(phi) - kappa lap(phi)
+      th[1] += (double)(dpsi_b<C>(p, ph) * lmt);
+      C gt = C(0);  // G^T lambda_{grad phi}, term by term as in grad_T
+#pragma unroll
+      for (int d = 1; d < 9; ++d) {
+        const C t = cy_of(d) == 0   ? C(cx_of(d)) * in.gpx[d - 1]
+                    : cx_of(d) == 0 ? C(cy_of(d)) * in.gpy[d - 1]
+                                    : C(cx_of(d)) * in.gpx[d - 1] + C(cy_of(d)) * in.gpy[d - 1];
+        gt += C(INV_CS2 * w_of(d)) * t;
+      }
+      const C lphi = in.lphi + gt + C(p.beta4 * 0.25) * d2psi_b<C>(p, ph) * lmt - C(p.kappa) * lt;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = k1 * in.a[j] + lphi;
+    };
+    constexpr int NR = KM_TY / (KM_THREADS / KM_TX);  // rows per thread
+    const int ty0 = threadIdx.x / KM_TX;
+    RowIn in[2];
+    load_row(ty0, in[0]);
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      if (r + 1 < NR) load_row(ty0 + (r + 1) * (KM_THREADS / KM_TX), in[(r + 1) & 1]);
+      finish_row(ty0 + r * (KM_THREADS / KM_TX), in[r & 1]);
     }
-    lt -= C(2.0 * INV_CS2 * (1.0 - w_of(0))) * lmt;
-    // forward phi around the cell for lap(phi) and psi
-    C v[3][3];
-    const int xs[3] = {stencil_idx(x - 1, p.nx, p.bcx), x, stencil_idx(x + 1, p.nx, p.bcx)};
-    const int ys[3] = {stencil_idx(y - 1, p.ny, p.bcy), y, stencil_idx(y + 1, p.ny, p.bcy)};
+  } else {
+    for (int ty = threadIdx.x / KM_TX; ty < KM_TY; ty += KM_THREADS / KM_TX) {
+      const int y = y0 + ty;
+      if (x >= p.nx || y >= p.ny) continue;
+      const unsigned kd = (unsigned)(y * p.nx + x);
+      const int lx = tx + 1, ly = ty + 1;
+      const C lmt = mt[ly][lx];
+      // L^T lambda_mu_tot from LDS
+      C lt = C(0);
+      if (single_pre(x, p.nx, p.bcx) && single_pre(y, p.ny, p.bcy)) {
 #pragma unroll
-    for (int a = 0; a < 3; ++a)
+        for (int d = 1; d < 9; ++d) lt += C(2.0 * INV_CS2 * w_of(d)) * mt[ly - cy_of(d)][lx - cx_of(d)];
+      } else {
 #pragma unroll
-      for (int b = 0; b < 3; ++b) v[a][b] = dphi[(unsigned)(ys[a] * p.pitch + xs[b])] + C(p.phi_ref);
-    const C ph = v[1][1];
-    th[0] += (double)(-lap_fwd<C>(v) * lmt);  // mu = psi'(phi) - kappa lap(phi)
-    th[1] += (double)(dpsi_b<C>(p, ph) * lmt);
-    const C lphi = w.lphi[kd] + grad_T<C>(p, w.lgpx, w.lgpy, x, y) +
-                   C(p.beta4 * 0.25) * d2psi_b<C>(p, ph) * lmt - C(p.kappa) * lt;
-    const C k1 = C(1.0 - p.omega_f);
-#pragma unroll
-    for (int j = 0; j < 9; ++j) {
-      C a = C(0);
-      if (!INIT) {
-        int qx = x + cx_of(j), qy = y + cy_of(j);
-        const bool wall = (p.bcx && (qx < 0 || qx >= p.nx)) || (p.bcy && (qy < 0 || qy >= p.ny));
-        qx = qx < 0 ? qx + p.nx : (qx >= p.nx ? qx - p.nx : qx);
-        qy = qy < 0 ? qy + p.ny : (qy >= p.ny ? qy - p.ny : qy);
-        const unsigned k = wall ? kd : (unsigned)(qy * p.nx + qx);
-        const auto la = wall ? uni(lam_in + opp_of(j) * n) : uni(lam_in + j * n);
-        a = la[k];
+        for (int d = 1; d < 9; ++d) {
+          int ox[2], oy[2];
+          const int nxo = pre_off(x, cx_of(d), p.nx, p.bcx, ox);
+          const int nyo = pre_off(y, cy_of(d), p.ny, p.bcy, oy);
+          for (int a = 0; a < nyo; ++a)
+            for (int b = 0; b < nxo; ++b) lt += C(2.0 * INV_CS2 * w_of(d)) * mt[ly + oy[a]][lx + ox[b]];
+        }
       }
-      uni(lam_out + j * n)[kd] = k1 * a + lphi;
+      lt -= C(2.0 * INV_CS2 * (1.0 - w_of(0))) * lmt;
+      // forward phi around the cell for lap(phi) and psi
+      C v[3][3];
+      const int xs[3] = {stencil_idx(x - 1, p.nx, p.bcx), x, stencil_idx(x + 1, p.nx, p.bcx)};
+      const int ys[3] = {stencil_idx(y - 1, p.ny, p.bcy), y, stencil_idx(y + 1, p.ny, p.bcy)};
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b) v[a][b] = dphi[(unsigned)(ys[a] * p.pitch + xs[b])] + C(p.phi_ref);
+      const C ph = v[1][1];
+      th[0] += (double)(-lap_fwd<C>(v) * lmt);  // mu = psi'(phi) - kappa lap(phi)
+      th[1] += (double)(dpsi_b<C>(p, ph) * lmt);
+      const C lphi = w.lphi[kd] + grad_T<C>(p, w.lgpx, w.lgpy, x, y) +
+                     C(p.beta4 * 0.25) * d2psi_b<C>(p, ph) * lmt - C(p.kappa) * lt;
+#pragma unroll
+      for (int j = 0; j < 9; ++j) {
+        C a = C(0);
+        if (!INIT) {
+          int qx = x + cx_of(j), qy = y + cy_of(j);
+          const bool wall = (p.bcx && (qx < 0 || qx >= p.nx)) || (p.bcy && (qy < 0 || qy >= p.ny));
+          qx = qx < 0 ? qx + p.nx : (qx >= p.nx ? qx - p.nx : qx);
+          qy = qy < 0 ? qy + p.ny : (qy >= p.ny ? qy - p.ny : qy);
+          const unsigned k = wall ? kd : (unsigned)(qy * p.nx + qx);
+          const auto la = wall ? uni(lam_in + opp_of(j) * n) : uni(lam_in + j * n);
+          a = la[k];
+        }
+        uni(lam_out + j * n)[kd] = k1 * a + lphi;
+      }
     }
   }
   block_sum_add<2>(th, th_part + (long long)tile * NTH + 0);
