@@ -75,7 +75,7 @@ class _Rollout(torch.autograd.Function):
         other = sim.new_adjoint()
         # phi = sum_i f_i, so dL/df_i = dL/dphi for every i
         lam[:9] = grad_phiN.to(lam.dtype).unsqueeze(0)
-        snaps = [sim.new_snapshot() for _ in range(min(K, nsteps))]
+        snaps = [sim.new_snapshot(zeroed=False) for _ in range(min(K, nsteps))]
         for seg, s0 in reversed(list(enumerate(range(0, nsteps, K)))):
             L = min(K, nsteps - s0)
             # recompute the segment's states and walk it backwards in one call

@@ -166,8 +166,12 @@ class Sim:
     def snapshot_bytes(self) -> int:
         return int(self.L.lbm_snapshot_bytes(self.ctx))
 
-    def new_snapshot(self) -> torch.Tensor:
-        return torch.zeros(self.snapshot_bytes(), dtype=torch.uint8, device=self.device)
+    def new_snapshot(self, zeroed: bool = True) -> torch.Tensor:
+        """A snapshot buffer.  zeroed=False leaves the row and plane padding
+        (never read by the kernels) undefined, which only matters to a
+        bytewise comparison of raw snapshots."""
+        alloc = torch.zeros if zeroed else torch.empty
+        return alloc(self.snapshot_bytes(), dtype=torch.uint8, device=self.device)
 
     def snapshot(self, out: Optional[torch.Tensor] = None) -> torch.Tensor:
         out = self.new_snapshot() if out is None else out
