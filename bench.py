@@ -253,6 +253,8 @@ def main():
     ap.add_argument("--no-two-kernel", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-K", type=int, default=100)
+    ap.add_argument("--adjoint-only", action="store_true",
+                    help="run only the adjoint leg and print its result (for profiling it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (--gpus {args.gpus} requested); the multi-GPU "
@@ -262,6 +264,10 @@ def main():
     import numpy as np
     import torch
     from paper_2311_10827_amd import inputs
+
+    if args.adjoint_only:
+        print(json.dumps({"adjoint": adjoint_leg(args.adjoint_steps, args.adjoint_K)}), flush=True)
+        return
 
     wl = inputs.THROUGHPUT
     dev = torch.device("cuda:0")
