@@ -90,20 +90,46 @@ def test_fp64_flat_interface_long_run(path):
     assert 1.4e-2 <= np.abs(gm["phi"] - phi0).max() <= 1.7e-2
 
 
-@pytest.mark.parametrize("path", PATHS)
-def test_fp64_coalescence_crop(path):
+def _crop():
     # 512 x 512 window of the 4096^2 two-drop field with seeded noise.
     wl = inputs.COALESCENCE
     x0, y0, w, h = wl.extra["crop"]
     full = inputs.two_drops(4096, 4096, wl.extra["R"], wl.W, noise=wl.extra["noise"], workload_id=3)
-    phi0 = np.ascontiguousarray(full[y0:y0 + h, x0:x0 + w])
-    say(f"[gpu] fp64 coalescence crop {phi0.shape} kernel_path={path}")
-    g = gpu_sim(wl, phi0, 64, kernel_path=path, nx=w, ny=h)
-    o = oracle_sim(wl, phi0, nx=w, ny=h)
-    g.step(300)
-    o.step(300)
-    compare_state(gpu_state(g), o.get_state(), TOL64)
-    compare_moments(gpu_moments(g)[0], o.moments(), TOL64)
+    return wl, np.ascontiguousarray(full[y0:y0 + h, x0:x0 + w]), dict(nx=w, ny=h)
+
+
+@pytest.fixture(scope="module")
+def crop_oracle_1000():
+    wl, phi0, over = _crop()
+    o = oracle_sim(wl, phi0, **over).step(1000)
+    return o.get_state(), o.moments()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_fp64_coalescence_crop(path, crop_oracle_1000):
+    wl, phi0, over = _crop()
+    say(f"[gpu] fp64 coalescence crop {phi0.shape} kernel_path={path}, 1000 steps")
+    g = gpu_sim(wl, phi0, 64, kernel_path=path, **over)
+    g.step(1000)
+    ostate, om = crop_oracle_1000
+    compare_state(gpu_state(g), ostate, TOL64)
+    compare_moments(gpu_moments(g)[0], om, TOL64)
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_fp32_coalescence_crop(path, crop_oracle_1000):
+    # the FP32 deviation-storage step against the FP64 oracle on the crop:
+    # phi within 1e-5, u within 1e-6 after 1000 steps
+    wl, phi0, over = _crop()
+    say(f"[gpu] fp32 coalescence crop kernel_path={path}, 1000 steps")
+    g = gpu_sim(wl, phi0, 32, kernel_path=path, **over)
+    g.step(1000)
+    gm, d = gpu_moments(g)
+    _, om = crop_oracle_1000
+    e_phi = np.abs(gm["phi"] - om["phi"]).max()
+    e_u = max(np.abs(gm["ux"] - om["ux"]).max(), np.abs(gm["uy"] - om["uy"]).max())
+    say(f"  phi err {e_phi:.3e}  u err {e_u:.3e}")
+    assert e_phi <= 1e-5 and e_u <= 1e-6
 
 
 def test_fp64_well_balanced_fixed_point():
