@@ -5,6 +5,8 @@ moment identity the paper states, a closed form, a physical limit recovered
 by the Chapman-Enskog analysis, a symmetry, or an independent fixture
 (the Newton-solved discrete equilibrium of ``equilibrium.py``).
 """
+import os
+
 import numpy as np
 import pytest
 
@@ -13,6 +15,16 @@ import oracle
 from paper_2311_10827_amd import inputs
 
 CX, CY, W, CS2 = oracle.lattice()
+
+
+def test_weights_match_the_printed_values():
+    # golden: the weights printed in Sec. 2.2, with |c_i|^2 of eq. ci
+    rows = np.loadtxt(os.path.join(os.path.dirname(__file__), "golden", "d2q9_weights.txt"))
+    cx, cy, w, cs2 = oracle.lattice()
+    for i, num, den, c2 in rows:
+        i = int(i)
+        assert w[i] == num / den
+        assert cx[i] ** 2 + cy[i] ** 2 == c2
 
 
 def test_lattice_isotropy():

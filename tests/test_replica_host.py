@@ -1,8 +1,39 @@
 """Host-side set-up of the paper's static test cases (Sec. 3.1, 3.2)."""
+import os
+
 import numpy as np
 import pytest
 
 from paper_2311_10827_amd import replica
+
+
+def _printed():
+    path = os.path.join(os.path.dirname(__file__), "golden", "paper_static_cases.txt")
+    out = {}
+    with open(path) as fh:
+        for line in fh:
+            line = line.split("#")[0].split()
+            if line:
+                out[line[0]] = float(line[1])
+    return out
+
+
+def test_cases_use_the_printed_parameters():
+    g = _printed()
+    wl, phi0 = replica.workload("flat", 10.0)
+    assert (wl.nx, wl.ny) == (g["flat_Lx"], g["flat_Ly"])
+    col = phi0[:, 0]
+    for key in ("flat_y1_over_Ly", "flat_y2_over_Ly"):
+        y = int(g[key] * g["flat_Ly"])
+        assert abs(col[y] - 0.5) < 1e-12       # the interfaces sit at y1 and y2
+    wl2, phi2 = replica.workload("droplet", 10.0)
+    L = int(g["droplet_L"])
+    assert (wl2.nx, wl2.ny) == (L, L)
+    c, R = int(g["droplet_xc_over_L"] * L), g["droplet_R_over_L"] * L
+    assert abs(phi2[c, c + int(R)] - 0.5) < 1e-12
+    for w in (wl, wl2):
+        assert w.rho_B == g["rho_v"] and w.nu_B == g["nu_v"]
+        assert (w.M, w.alpha, w.sigma, w.W) == (g["M_phi"], g["alpha"], g["sigma"], g["W"])
 
 
 @pytest.mark.parametrize("case,shape", [("flat", (128, 32)), ("droplet", (128, 128))])
