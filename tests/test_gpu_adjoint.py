@@ -226,3 +226,49 @@ def test_fp32_gradient_close_to_fp64():
     say(f"  theta fp64 {g64[0]}\n  theta fp32 {g32[0]}")
     assert np.all(np.abs(g32[0] - g64[0]) <= 2e-3 * np.abs(g64[0]) + 1e-9 * np.abs(g64[0]).max())
     assert np.abs(g32[1] - g64[1]).max() <= 2e-3 * np.abs(g64[1]).max()
+
+
+@pytest.mark.parametrize("k", range(6))
+def test_dot_product_random_configuration(k):
+    # one step's transpose on seeded random configurations: sizes, walls,
+    # both phi conventions, densities, viscosities, alpha and a body force
+    rng = np.random.default_rng(231110827 + 2000 + k)
+    nx, ny = int(rng.integers(3, 30)), int(rng.integers(3, 30))
+    bcx, bcy = int(rng.integers(2)), int(rng.integers(2))
+    phi_B = float(rng.choice([-1.0, 0.0]))
+    wl = inputs.Workload(f"adj_random_{k}", nx, ny, bc_x=bcx, bc_y=bcy, phi_A=1.0, phi_B=phi_B,
+                         rho_A=float(rng.choice([1.0, 10.0, 100.0])), rho_B=1.0,
+                         nu_A=float(rng.uniform(0.03, 0.2)), nu_B=float(rng.uniform(0.03, 0.2)),
+                         sigma=float(rng.uniform(1e-3, 1e-2)), W=4.0,
+                         M=float(rng.uniform(0.03, 0.2)), alpha=float(rng.choice([0.5, 1.0, 2.0])))
+    gx, gy = (float(v) for v in rng.uniform(-1e-5, 1e-5, size=2))
+    prm = oracle.params_for(wl, gx=gx, gy=gy)
+    phi0 = inputs.two_drops(nx, ny, max(1.0, 0.2 * min(nx, ny)), 4.0, noise=1e-3, workload_id=2000 + k,
+                            phi_A=1.0, phi_B=phi_B)
+    f, g, Sp = oracle.Sim(prm).init(phi0).step(3).get_state()
+    gp = make_params(wl, precision=64, kappa=prm.kappa, beta=prm.beta, gx=gx, gy=gy)
+    say(f"[gpu] adjoint dot product, random case {k}: {nx}x{ny} bc=({bcx},{bcy}) phi_B={phi_B}")
+    sim = Sim(gp, phi0)
+    sim.set_state(f, g, Sp)
+    sim.enable_adjoint()
+    snap = sim.snapshot()
+    lam1 = rng.standard_normal((19, ny, nx))
+    lout = sim.new_adjoint()
+    sim.adjoint_step(snap, torch.from_numpy(lam1).cuda(), lout)
+    g6 = np.array(sim.adjoint_theta(reset=True))
+    lam0 = lout.cpu().numpy()
+    df = rng.standard_normal(f.shape) * 1e-3
+    dg = rng.standard_normal(g.shape) * 1e-5
+    dS = rng.standard_normal(Sp.shape) * 1e-6
+    t = oracle.TLM(prm).set_state(f, df, g, dg, Sp, dS).step(1)
+    _, Jf, _, Jg, _, JS = t.get_state()
+    lhs, rhs = _dot(lam1, _lam_pack(Jf, Jg, JS)), _dot(lam0, _lam_pack(df, dg, dS))
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300), (lhs, rhs)
+    scales = np.array([1e-3, 1e-4, 0.1, 0.05, 0.01, 0.01])
+    for q in range(6):
+        dth = np.zeros(6)
+        dth[q] = scales[q]
+        t = oracle.TLM(prm, dth).set_state(f, None, g, None, Sp, None).step(1)
+        _, Jf, _, Jg, _, JS = t.get_state()
+        lhs = _dot(lam1, _lam_pack(Jf, Jg, JS))
+        assert abs(lhs - g6[q] * scales[q]) <= 1e-11 * max(abs(lhs), 1e-300), (THETA[q], lhs, g6[q] * scales[q])
