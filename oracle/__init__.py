@@ -28,6 +28,8 @@ _SRC = os.path.join(_HERE, "lbm_oracle.cpp")
 _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 
 PERIODIC, WALL = 0, 1
+# viscosity across the interface: nu, 1/nu or ln nu linear in phi (Sec. 2.3.2)
+NU_LINEAR, NU_INVERSE, NU_EXP = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -51,6 +53,7 @@ class OrcParams(ctypes.Structure):
         ("kappa", ctypes.c_double), ("beta", ctypes.c_double),
         ("M", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
+        ("nu_form", ctypes.c_int32),
     ]
 
 
@@ -73,11 +76,12 @@ class Params:
     alpha: float = 1.0
     gx: float = 0.0
     gy: float = 0.0
+    nu_form: int = NU_LINEAR
 
     def c(self) -> OrcParams:
         return OrcParams(self.nx, self.ny, self.bc_x, self.bc_y, self.phi_A, self.phi_B,
                          self.rho_A, self.rho_B, self.nu_A, self.nu_B, self.kappa, self.beta,
-                         self.M, self.alpha, self.gx, self.gy)
+                         self.M, self.alpha, self.gx, self.gy, self.nu_form)
 
     @property
     def tau_f(self) -> float:
@@ -327,6 +331,7 @@ def params_for(wl, nx=None, ny=None, **over) -> Params:
     kappa, beta = kappa_beta(wl.sigma, wl.W, abs(wl.phi_A - wl.phi_B))
     kw = dict(nx=nx or wl.nx, ny=ny or wl.ny, bc_x=wl.bc_x, bc_y=wl.bc_y, phi_A=wl.phi_A,
               phi_B=wl.phi_B, rho_A=wl.rho_A, rho_B=wl.rho_B, nu_A=wl.nu_A, nu_B=wl.nu_B,
-              kappa=kappa, beta=beta, M=wl.M, alpha=wl.alpha)
+              kappa=kappa, beta=beta, M=wl.M, alpha=wl.alpha,
+              nu_form=getattr(wl, "nu_form", NU_LINEAR))
     kw.update(over)
     return Params(**kw)

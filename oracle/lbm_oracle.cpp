@@ -11,7 +11,8 @@
 // the paper's order and notation, one full-grid pass per step, with no
 // fusion or blocking:
 //   1. order parameter phi = sum_i f_i                      (Sec. 2.3.1, eq. order-parameter)
-//   2. density and viscosity, linear in phi                 (Sec. 2.3.2, eq. vis and the sentence before it)
+//   2. density and viscosity, linear in phi                 (Sec. 2.3.2, eq. vis and the sentence before it;
+//      the viscosity optionally in the inverse-linear or exponential form named there)
 //   3. chemical potential mu = psi'(phi) - kappa lap(phi)   (Sec. 2.1, eq. chemical_potencial; Sec. 2.3.2, eq. Laplace)
 //   4. isotropic gradients of phi, mu and rho               (Sec. 2.3.2, eq. gradient)
 //   5. force F = -phi grad(mu) + G                          (Sec. 2.1 after eq. 6; Sec. 2.3.2 after eq. GGi)
@@ -29,6 +30,10 @@
 //    [F_i(t) - F_i(t-1)]/delta_t, which needs S of the previous step.
 //  * rho(phi) and nu(phi) are linear between (phi_B, rho_B|nu_B) and
 //    (phi_A, rho_A|nu_A); tau_g = 1/2 + nu/c_s^2 per cell (Sec. 2.3.2).
+//    The inverse-linear and exponential viscosity forms, which the paper
+//    names without writing them out, are read as 1/nu, respectively ln nu,
+//    linear in the same phase-A fraction s = (phi - phi_B)/(phi_A - phi_B),
+//    with no clamping of s (as for the linear form).
 //  * tau_f = 1/2 + M/(c_s^2 alpha) (Sec. 2.3.1, eq. mobility).
 //  * Walls: half-way bounce-back for f and g; ghost values of phi and mu
 //    across a wall mirror the adjacent cell (the paper's tests are periodic).
@@ -81,6 +86,14 @@ inline Dual& operator+=(Dual& a, Dual b) { a = a + b; return a; }
 inline Dual& operator-=(Dual& a, Dual b) { a = a - b; return a; }
 inline double val(double a) { return a; }
 inline double val(Dual a) { return a.v; }
+// exp and ln with their exact derivatives, for the exponential viscosity form
+inline double expo(double a) { return std::exp(a); }
+inline Dual expo(Dual a) {
+  const double e = std::exp(a.v);
+  return Dual(e, e * a.d);
+}
+inline double logn(double a) { return std::log(a); }
+inline Dual logn(Dual a) { return Dual(std::log(a.v), a.d / a.v); }
 
 // ------------------------------------------------------------- D2Q9 lattice
 // Sec. 2.2, eq. eq:ci and the weights stated just after it.  Order used on
@@ -105,6 +118,8 @@ extern "C" {
 
 // Boundary kinds.
 enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
+// Viscosity across the interface: nu, 1/nu or ln nu linear in phi.
+enum { ORC_NU_LINEAR = 0, ORC_NU_INVERSE = 1, ORC_NU_EXP = 2 };
 
 typedef struct {
   int32_t nx, ny;
@@ -115,6 +130,7 @@ typedef struct {
   double kappa, beta;
   double M, alpha;      // tau_f = 1/2 + M/(c_s^2 alpha)
   double gx, gy;        // body force G
+  int32_t nu_form;      // ORC_NU_*
 } orc_params;
 
 }  // extern "C"
@@ -203,15 +219,24 @@ struct Sim {
       out[k] = 4.0 * th.beta * (ph[k] - pl) * (ph[k] - pv) * (ph[k] - pm) - th.kappa * lap[k];
   }
 
-  // Linear density and viscosity in phi (Sec. 2.3.2, eq. vis and the text before it).
-  // rho = rho_B + (phi - phi_B) (rho_A - rho_B) / (phi_A - phi_B), and the same for nu
+  // Linear density in phi (Sec. 2.3.2, the text before eq. vis):
+  // rho = rho_B + (phi - phi_B) (rho_A - rho_B) / (phi_A - phi_B).
   R density(R ph) const {
     const double slope = (p.rho_A - p.rho_B) / (p.phi_A - p.phi_B);
     return p.rho_B + (ph - p.phi_B) * slope;
   }
+  // Kinematic viscosity.  Linear in phi as the paper adopts it (eq. vis), the
+  // same line as for rho; or one of the two alternatives it names in Sec. 2.3.2
+  // (inverse-linear, exponential), written with the phase-A fraction s.
   R viscosity(R ph) const {
-    const R slope = (th.nu_A - th.nu_B) / (p.phi_A - p.phi_B);
-    return th.nu_B + (ph - p.phi_B) * slope;
+    if (p.nu_form == ORC_NU_LINEAR) {
+      const R slope = (th.nu_A - th.nu_B) / (p.phi_A - p.phi_B);
+      return th.nu_B + (ph - p.phi_B) * slope;
+    }
+    const R s = (ph - p.phi_B) / (p.phi_A - p.phi_B);
+    if (p.nu_form == ORC_NU_INVERSE) return 1.0 / (s / th.nu_A + (1.0 - s) / th.nu_B);
+    if (p.nu_form == ORC_NU_EXP) return expo(s * logn(th.nu_A) + (1.0 - s) * logn(th.nu_B));
+    std::abort();
   }
 
   // Sec. 2.3.1, eq. H_i.

@@ -297,6 +297,35 @@ def test_shear_wave_decay(phase):
     assert rate == pytest.approx(nu * k * k, rel=5e-3)
 
 
+@pytest.mark.parametrize("form", [oracle.NU_LINEAR, oracle.NU_INVERSE, oracle.NU_EXP])
+@pytest.mark.parametrize("s_A", [0.0, 0.25, 0.5, 1.0])
+def test_shear_wave_decay_viscosity_forms(form, s_A):
+    # A uniform phi is a fixed point of the order-parameter update (grad phi,
+    # grad mu and the source all vanish), so a transverse wave in it decays at
+    # nu(phi) k^2.  With s_A the phase-A fraction, the three forms of Sec. 2.3.2
+    # make nu the weighted arithmetic, harmonic and geometric mean of nu_A and
+    # nu_B; between the phases they differ by up to a factor of three here.
+    nx, ny = 64, 2
+    k = 2 * np.pi / nx
+    nu_A, nu_B = 0.02, 0.2
+    prm = oracle.Params(nx=nx, ny=ny, rho_A=3.0, rho_B=1.0, nu_A=nu_A, nu_B=nu_B,
+                        kappa=1e-3, beta=1e-3, nu_form=form)
+    phi = -1.0 + 2.0 * s_A
+    X = np.broadcast_to(np.arange(nx, dtype=float), (ny, nx))
+    s = oracle.Sim(prm).init(np.full((ny, nx), phi), None, 1e-6 * np.sin(k * X))
+    amp = []
+    for _ in range(4):
+        s.step(200)
+        m = s.moments()
+        assert np.abs(m["phi"] - phi).max() < 1e-12  # rounding drift only
+        amp.append((m["uy"] * np.sin(k * X)).sum() / (np.sin(k * X) ** 2).sum())
+    rate = -np.log(amp[-1] / amp[0]) / 600
+    nu = {oracle.NU_LINEAR: s_A * nu_A + (1 - s_A) * nu_B,
+          oracle.NU_INVERSE: 1.0 / (s_A / nu_A + (1 - s_A) / nu_B),
+          oracle.NU_EXP: nu_A ** s_A * nu_B ** (1 - s_A)}[form]
+    assert rate == pytest.approx(nu * k * k, rel=5e-3)
+
+
 def test_sound_wave_speed():
     # Sound speed of the pressure-based NS-LBE (derived from Sec. 2.3.2,
     # eq. G_i and the pressure recovery): collision conserves
@@ -380,11 +409,14 @@ def test_mirror_symmetry_with_walls():
     assert np.abs(m["ux"]).max() > 1e-9
 
 
-def test_tlm_matches_central_differences():
+@pytest.mark.parametrize("form,nu_A,nu_B", [(oracle.NU_LINEAR, 0.1, 0.1), (oracle.NU_LINEAR, 0.05, 0.2),
+                                             (oracle.NU_INVERSE, 0.05, 0.2), (oracle.NU_EXP, 0.05, 0.2)])
+def test_tlm_matches_central_differences(form, nu_A, nu_B):
     # The dual-number instantiation is the exact tangent of the FP64 step;
     # check it against central differences of the plain oracle.
     rng = np.random.default_rng(5)
-    prm = oracle.params_for(inputs.ADJOINT, nx=16, ny=12, bc_x=oracle.WALL)
+    prm = oracle.params_for(inputs.ADJOINT, nx=16, ny=12, bc_x=oracle.WALL, nu_form=form,
+                            nu_A=nu_A, nu_B=nu_B)
     phi0 = inputs.two_drops(16, 12, 3.0, 4.0, noise=1e-2)
     s = oracle.Sim(prm).init(phi0).step(3)
     f, g, Sp = s.get_state()
