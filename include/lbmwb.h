@@ -52,13 +52,16 @@ extern "C" {
 
 enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
 
+/* Viscosity across the interface (lbm_params.nu_form). */
+enum { LBM_NU_LINEAR = 0, LBM_NU_INVERSE = 1, LBM_NU_EXP = 2 };
+
 /*
  * Problem parameters, in the paper's notation.
  *   phi_A, phi_B   order parameter of the two bulk phases (Sec. 2.1, eq. bulk_energy).
  *   rho_A, rho_B   densities; rho is linear in phi between them (Sec. 2.3.2,
  *                  sentence before eq. vis).
- *   nu_A, nu_B     kinematic viscosities; nu is linear in phi (eq. vis) and
- *                  tau_g = 1/2 + nu / c_s^2 per cell (Sec. 2.3.2).
+ *   nu_A, nu_B     kinematic viscosities; tau_g = 1/2 + nu / c_s^2 per cell
+ *                  (Sec. 2.3.2), with nu(phi) chosen by nu_form.
  *   kappa, beta    gradient and double-well coefficients (eqs. energy_function,
  *                  bulk_energy).  With use_sigma_W = 1 they are derived from the
  *                  surface tension sigma and interface width W instead
@@ -83,6 +86,17 @@ enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
  *                  1: the phi/mu pass and the collide-stream pass as two
  *                  kernels; 2: one fused kernel per step (phi and mu kept
  *                  on chip).  All give the same results bit for bit.
+ *   nu_form        how nu varies across the interface (Sec. 2.3.2).  With the
+ *                  phase-A fraction s = (phi - phi_B)/(phi_A - phi_B):
+ *                  LBM_NU_LINEAR:  nu linear in phi (eq. vis, the paper's
+ *                                  choice);
+ *                  LBM_NU_INVERSE: 1/nu = s/nu_A + (1 - s)/nu_B;
+ *                  LBM_NU_EXP:     ln nu = s ln nu_A + (1 - s) ln nu_B.
+ *                  The paper names the last two as alternatives without
+ *                  writing them out; s is not clamped.  1/nu vanishes at
+ *                  s = -nu_A/(nu_B - nu_A) when nu_A < nu_B (and mirrored),
+ *                  so the inverse form needs phi to stay that close to the
+ *                  bulk values.
  */
 typedef struct lbm_params {
   int32_t nx, ny;
@@ -98,6 +112,7 @@ typedef struct lbm_params {
   double gx, gy;
   int32_t diag_every;
   int32_t kernel_path;
+  int32_t nu_form;
 } lbm_params;
 
 /* Derived constants (lattice units). */
@@ -133,7 +148,8 @@ typedef struct lbm_ctx lbm_ctx;
 /* Validate `p` and fill `out`.  LBM_EINVAL on: nx, ny < 1; a plane of more
  * than 2^31 - 1 cells; bc not 0/1; precision not 32/64; phi_A == phi_B;
  * rho_A, rho_B <= 0; nu_A, nu_B <= 0; M <= 0; alpha <= 0; kappa or beta
- * < 0 (or sigma, W <= 0 with use_sigma_W); diag_every < 0. */
+ * < 0 (or sigma, W <= 0 with use_sigma_W); diag_every < 0; kernel_path not
+ * 0..2; nu_form not one of LBM_NU_*. */
 int lbm_derive(const lbm_params* p, lbm_derived* out);
 
 /* Bytes the caller must allocate for the state and the workspace (0 if `p`

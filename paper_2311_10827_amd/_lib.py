@@ -39,6 +39,7 @@ class LbmParams(ctypes.Structure):
         ("M", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("diag_every", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
+        ("nu_form", ctypes.c_int32),
     ]
 
 

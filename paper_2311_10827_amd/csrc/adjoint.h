@@ -226,7 +226,7 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   const C grx = rs * gpx, gry = rs * gpy;
   const C dB = phi - C(p.phiB);
   const C rho = C(p.rhoB) + dB * rs;
-  const C nu = C(p.nuB) + dB * C(p.nu_slope);
+  const C nu = visc<C>(p, dB);
   const C tau = half + three * nu;
   const C wg = one / tau, kG = one - half * wg;
   const C Fx = C(p.gx) - phi * gmx, Fy = C(p.gy) - phi * gmy;
@@ -313,10 +313,11 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   // tau_g = 1/2 + 3 nu(phi); w_g = 1/tau_g; k_G = 1 - w_g/2
   const C lwg_t = lwg - half * lkG;
   const C lnu = three * (-(wg * wg) * lwg_t);
-  lphi += lnu * C(p.nu_slope);
-  const C t = dB * C(1.0 / (p.phiA - p.phiB));
-  th[2] += (double)(lnu * t);
-  th[3] += (double)(lnu * (one - t));
+  C dnu_phi, dnu_A, dnu_B;
+  visc_partials<C>(p, dB, nu, dnu_phi, dnu_A, dnu_B);
+  lphi += lnu * dnu_phi;
+  th[2] += (double)(lnu * dnu_A);
+  th[3] += (double)(lnu * dnu_B);
   // S = u . grad phi
   lux += lSt * gpx;
   luy += lSt * gpy;

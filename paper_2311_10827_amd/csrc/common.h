@@ -67,9 +67,53 @@ struct KP {
   double kappa, alpha;
   double omega_f;               // 1 / tau_f
   double rhoB, rho_slope;       // rho = rho_B + (phi - phi_B) rho_slope
-  double nuB, nu_slope;         // nu  = nu_B  + (phi - phi_B) nu_slope
+  double nuB, nu_slope;         // nu  = nu_B  + (phi - phi_B) nu_slope (linear form)
   double gx, gy;
+  int nu_form;                  // NU_LINEAR, NU_INVERSE or NU_EXP
+  double dphiAB;                // phi_A - phi_B
+  double nuA, ln_nuA, ln_nuB;   // for the inverse-linear and exponential forms
+  double nu_dphi;               // d nu/d phi over nu^2 (inverse) or over nu (exponential)
+  double inv_nuA, inv_nuB;      // 1/nu_A, 1/nu_B
 };
+
+// Viscosity across the interface (Sec. 2.3.2).  The paper adopts nu linear in
+// phi (eq. vis); it names the inverse-linear and the exponential forms as the
+// alternatives, read here as 1/nu, respectively ln nu, linear in the phase-A
+// fraction s = (phi - phi_B)/(phi_A - phi_B).
+enum { NU_LINEAR = 0, NU_INVERSE = 1, NU_EXP = 2 };
+
+// nu at a cell from dB = phi - phi_B.  The form is uniform over a launch.
+template <typename C>
+__device__ __forceinline__ C visc(const KP& p, C dB) {
+  if (p.nu_form == NU_LINEAR) return C(p.nuB) + dB * C(p.nu_slope);
+  const C s = dB / C(p.dphiAB);
+  if (p.nu_form == NU_INVERSE) return C(1) / (s / C(p.nuA) + (C(1) - s) / C(p.nuB));
+  const C e = s * C(p.ln_nuA) + (C(1) - s) * C(p.ln_nuB);
+  if constexpr (std::is_same<C, float>::value)
+    return expf(e);
+  else
+    return exp(e);
+}
+
+// d nu/d phi, d nu/d nu_A and d nu/d nu_B at a cell, from dB and nu = visc(dB).
+template <typename C>
+__device__ __forceinline__ void visc_partials(const KP& p, C dB, C nu, C& d_phi, C& d_A, C& d_B) {
+  const C s = dB * C(1.0 / p.dphiAB);
+  if (p.nu_form == NU_LINEAR) {
+    d_phi = C(p.nu_slope);
+    d_A = s;
+    d_B = C(1) - s;
+  } else if (p.nu_form == NU_INVERSE) {  // nu = 1/q, q = s/nu_A + (1 - s)/nu_B
+    const C n2 = nu * nu;
+    d_phi = n2 * C(p.nu_dphi);
+    d_A = n2 * s * C(p.inv_nuA * p.inv_nuA);
+    d_B = n2 * (C(1) - s) * C(p.inv_nuB * p.inv_nuB);
+  } else {  // ln nu = s ln nu_A + (1 - s) ln nu_B
+    d_phi = nu * C(p.nu_dphi);
+    d_A = nu * s * C(p.inv_nuA);
+    d_B = nu * (C(1) - s) * C(p.inv_nuB);
+  }
+}
 
 // XCD-aware tile order: the hardware deals workgroups round-robin over the
 // 8 XCDs, so each XCD gets one contiguous band of tiles and neighbouring

@@ -149,7 +149,8 @@ __global__ __launch_bounds__(256) void k_phi_mu(const KP p, const T* __restrict_
 // Per cell: gather f_i, g_i (pull streaming with bounce-back), read the 3x3
 // neighbourhoods of phi and mu, and apply
 //   grad phi, grad mu, grad rho (Sec. 2.3.2, eq. gradient);
-//   rho, nu linear in phi (Sec. 2.3.2, eq. vis), tau_g = 1/2 + nu / c_s^2;
+//   rho linear in phi, nu linear (Sec. 2.3.2, eq. vis) or in one of the two
+//     alternative forms named there, tau_g = 1/2 + nu / c_s^2;
 //   F = -phi grad mu + G (Sec. 2.1 after eq. 6; Sec. 2.3.2 after eq. GGi);
 //   rho u = sum c_i g_i + F/2, p = c_s^2/(1-w_0)[sum_{i!=0} g_i + u.grad(rho)/2
 //     + rho s_0(u)] (Sec. 2.3.2, macroscopic subequations);
@@ -203,7 +204,7 @@ __device__ __forceinline__ void cell_f64(const KP& p, const Pops<double>& q, con
 #pragma unroll
     for (int b = 0; b < 3; ++b) rho3[a][b] = p.rhoB + (n.ph[a][b] - p.phiB) * p.rho_slope;
   const double phi = n.ph[1][1], mu = n.mu[1][1], rho = rho3[1][1];
-  const double nu = p.nuB + (phi - p.phiB) * p.nu_slope;
+  const double nu = visc<double>(p, phi - p.phiB);
   double gpx, gpy, gmx, gmy, grx, gry;
   grad_f64(n.ph, gpx, gpy);
   grad_f64(n.mu, gmx, gmy);
@@ -307,7 +308,7 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
 #pragma unroll
   for (int i = 1; i < 9; ++i)
     fo[i] = f[i] + wf * ((float)w_of(i) * am - f[i]) + (float)(w_of(i) * src_bracket(i)) * src;
-  const float tau = 0.5f + 3.0f * ((float)p.nuB + dB * (float)p.nu_slope);
+  const float tau = 0.5f + 3.0f * visc<float>(p, dB);
   const float wg = 1.0f / tau;
   const float kG = 1.0f - 0.5f * wg;
   const float ge0 = -(float)(5.0 / 3.0) * pr - (float)(2.0 / 3.0) * rho * uu;

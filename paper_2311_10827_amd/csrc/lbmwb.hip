@@ -68,6 +68,7 @@ int validate(const lbm_params* p, lbm_derived* d) {
   if (p->precision != 32 && p->precision != 64) return LBM_EINVAL;
   if (p->diag_every < 0) return LBM_EINVAL;
   if (p->kernel_path < 0 || p->kernel_path > 2) return LBM_EINVAL;
+  if (p->nu_form < LBM_NU_LINEAR || p->nu_form > LBM_NU_EXP) return LBM_EINVAL;
   const size_t pitch = round_up((size_t)p->nx, 64);
   if (pitch * (size_t)p->ny > (size_t)INT32_MAX) return LBM_EINVAL;
   const double dphi = p->phi_A - p->phi_B;
@@ -560,6 +561,15 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   k.nu_slope = (p->nu_A - p->nu_B) / (p->phi_A - p->phi_B);
   k.gx = p->gx;
   k.gy = p->gy;
+  k.nu_form = p->nu_form;
+  k.dphiAB = p->phi_A - p->phi_B;
+  k.nuA = p->nu_A;
+  k.ln_nuA = std::log(p->nu_A);
+  k.ln_nuB = std::log(p->nu_B);
+  k.inv_nuA = 1.0 / p->nu_A;
+  k.inv_nuB = 1.0 / p->nu_B;
+  k.nu_dphi = p->nu_form == LBM_NU_INVERSE ? (k.inv_nuB - k.inv_nuA) / k.dphiAB
+                                           : (k.ln_nuA - k.ln_nuB) / k.dphiAB;
   hipError_t e = hipHostMalloc((void**)&c->diag_host, 2 * NQ * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;

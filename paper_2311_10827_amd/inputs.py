@@ -168,6 +168,7 @@ class Workload:
     W: float = 4.0
     M: float = 0.05
     alpha: float = 1.0
+    nu_form: int = 0       # 0 nu, 1 1/nu, 2 ln nu linear in phi
     steps: int = 1000
     extra: dict = field(default_factory=dict)
 

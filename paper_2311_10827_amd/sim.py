@@ -13,6 +13,9 @@ import torch
 from . import _lib
 from ._lib import LbmDiag, LbmParams, LbmDerived, check
 
+# viscosity across the interface (lbm_params.nu_form): nu, 1/nu or ln nu linear in phi
+NU_LINEAR, NU_INVERSE, NU_EXP = 0, 1, 2
+
 
 def make_params(workload=None, precision: int = 64, diag_every: int = 0, **over) -> LbmParams:
     """C parameter block from a workload preset (``inputs.Workload``) and overrides.
@@ -23,10 +26,10 @@ def make_params(workload=None, precision: int = 64, diag_every: int = 0, **over)
     kw = dict(nx=0, ny=0, bc_x=0, bc_y=0, precision=precision, use_sigma_W=0, phi_A=1.0,
               phi_B=-1.0, rho_A=1.0, rho_B=1.0, nu_A=0.1, nu_B=0.1, kappa=0.0, beta=0.0,
               sigma=0.0, W=0.0, M=0.1, alpha=1.0, gx=0.0, gy=0.0, diag_every=diag_every,
-              kernel_path=0)
+              kernel_path=0, nu_form=NU_LINEAR)
     if workload is not None:
         for k in ("nx", "ny", "bc_x", "bc_y", "phi_A", "phi_B", "rho_A", "rho_B", "nu_A", "nu_B",
-                  "sigma", "W", "M", "alpha"):
+                  "sigma", "W", "M", "alpha", "nu_form"):
             kw[k] = getattr(workload, k)
         kw["use_sigma_W"] = 1
     if "kappa" in over or "beta" in over:

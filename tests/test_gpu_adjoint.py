@@ -272,3 +272,41 @@ def test_dot_product_random_configuration(k):
         _, Jf, _, Jg, _, JS = t.get_state()
         lhs = _dot(lam1, _lam_pack(Jf, Jg, JS))
         assert abs(lhs - g6[q] * scales[q]) <= 1e-11 * max(abs(lhs), 1e-300), (THETA[q], lhs, g6[q] * scales[q])
+
+
+@pytest.mark.parametrize("form", [0, 1, 2])
+def test_dot_product_viscosity_forms(form):
+    # one step's transpose with nu linear, inverse-linear or exponential in phi
+    # (Sec. 2.3.2) at a viscosity ratio of 10, walls in x
+    nx, ny = 23, 17
+    wl = inputs.Workload("adj_visc", nx, ny, bc_x=1, rho_A=10.0, rho_B=1.0, nu_A=0.03, nu_B=0.2,
+                         sigma=5e-3, W=4.0, M=0.05, nu_form=form)
+    prm = oracle.params_for(wl)
+    phi0 = inputs.two_drops(nx, ny, 4.0, 4.0, noise=1e-3, workload_id=21)
+    f, g, Sp = oracle.Sim(prm).init(phi0).step(3).get_state()
+    gp = make_params(wl, precision=64, kappa=prm.kappa, beta=prm.beta)
+    say(f"[gpu] adjoint dot product, viscosity form {form}")
+    sim = Sim(gp, phi0)
+    sim.set_state(f, g, Sp)
+    sim.enable_adjoint()
+    snap = sim.snapshot()
+    rng = np.random.default_rng(21 + form)
+    lam1 = rng.standard_normal((19, ny, nx))
+    lout = sim.new_adjoint()
+    sim.adjoint_step(snap, torch.from_numpy(lam1).cuda(), lout)
+    g6 = np.array(sim.adjoint_theta(reset=True))
+    lam0 = lout.cpu().numpy()
+    df = rng.standard_normal(f.shape) * 1e-3
+    dg = rng.standard_normal(g.shape) * 1e-5
+    dS = rng.standard_normal(Sp.shape) * 1e-6
+    _, Jf, _, Jg, _, JS = oracle.TLM(prm).set_state(f, df, g, dg, Sp, dS).step(1).get_state()
+    lhs, rhs = _dot(lam1, _lam_pack(Jf, Jg, JS)), _dot(lam0, _lam_pack(df, dg, dS))
+    say(f"  state: lhs {lhs:.16e} rhs {rhs:.16e}")
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300), (lhs, rhs)
+    for q, scale in ((4, 0.01), (5, 0.01)):
+        dth = np.zeros(6)
+        dth[q] = scale
+        _, Jf, _, Jg, _, JS = oracle.TLM(prm, dth).set_state(f, None, g, None, Sp, None).step(1).get_state()
+        lhs = _dot(lam1, _lam_pack(Jf, Jg, JS))
+        say(f"  {THETA[q]}: lhs {lhs:.16e} rhs {g6[q] * scale:.16e}")
+        assert abs(lhs - g6[q] * scale) <= 1e-11 * max(abs(lhs), 1e-300), (THETA[q], lhs, g6[q] * scale)
