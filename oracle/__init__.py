@@ -30,6 +30,8 @@ _LIB = os.path.join(_HERE, "liblbm_oracle.so")
 PERIODIC, WALL = 0, 1
 # viscosity across the interface: nu, 1/nu or ln nu linear in phi (Sec. 2.3.2)
 NU_LINEAR, NU_INVERSE, NU_EXP = 0, 1, 2
+# collision operator; MRT rates: f (e, eps, q, p), g ((rho, e, eps) together, q)
+BGK, MRT = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -54,6 +56,8 @@ class OrcParams(ctypes.Structure):
         ("M", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("nu_form", ctypes.c_int32),
+        ("collision", ctypes.c_int32),
+        ("mrt_f", ctypes.c_double * 4), ("mrt_g", ctypes.c_double * 2),
     ]
 
 
@@ -77,11 +81,15 @@ class Params:
     gx: float = 0.0
     gy: float = 0.0
     nu_form: int = NU_LINEAR
+    collision: int = BGK
+    mrt_f: tuple = (1.0, 1.0, 1.0, 1.0)
+    mrt_g: tuple = (1.0, 1.0)
 
     def c(self) -> OrcParams:
         return OrcParams(self.nx, self.ny, self.bc_x, self.bc_y, self.phi_A, self.phi_B,
                          self.rho_A, self.rho_B, self.nu_A, self.nu_B, self.kappa, self.beta,
-                         self.M, self.alpha, self.gx, self.gy, self.nu_form)
+                         self.M, self.alpha, self.gx, self.gy, self.nu_form, self.collision,
+                         (ctypes.c_double * 4)(*self.mrt_f), (ctypes.c_double * 2)(*self.mrt_g))
 
     @property
     def tau_f(self) -> float:
@@ -332,6 +340,8 @@ def params_for(wl, nx=None, ny=None, **over) -> Params:
     kw = dict(nx=nx or wl.nx, ny=ny or wl.ny, bc_x=wl.bc_x, bc_y=wl.bc_y, phi_A=wl.phi_A,
               phi_B=wl.phi_B, rho_A=wl.rho_A, rho_B=wl.rho_B, nu_A=wl.nu_A, nu_B=wl.nu_B,
               kappa=kappa, beta=beta, M=wl.M, alpha=wl.alpha,
-              nu_form=getattr(wl, "nu_form", NU_LINEAR))
+              nu_form=getattr(wl, "nu_form", NU_LINEAR), collision=getattr(wl, "collision", BGK),
+              mrt_f=tuple(getattr(wl, "mrt_f", (1.0, 1.0, 1.0, 1.0))),
+              mrt_g=tuple(getattr(wl, "mrt_g", (1.0, 1.0))))
     kw.update(over)
     return Params(**kw)

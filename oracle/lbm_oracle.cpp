@@ -39,6 +39,18 @@
 //    across a wall mirror the adjacent cell (the paper's tests are periodic).
 //  * Initial state: f = f^eq(phi0, mu(phi0)), g = g^eq(p=0, u0), and the
 //    previous-step source equals S computed from that state.
+//  * Multiple relaxation times (the paper only says BGK extends to them):
+//    both collisions relax the non-equilibrium part in the orthogonal moment
+//    basis of Lallemand and Luo, m = (rho, e, eps, j_x, q_x, j_y, q_y, p_xx,
+//    p_xy).  f: the fluxes j relax at 1/tau_f (the mobility of eq. mobility),
+//    rho at 1/tau_f, the others at given rates; its source is added as in BGK.
+//    g: j, p_xx, p_xy relax at 1/tau_g(phi), q at a given rate, and rho, e
+//    and eps at one common given rate: in this pressure form p is recovered
+//    from sum_{i!=0} g_i = (8 rho + e - eps)/9, which the collision must not
+//    change through unequal rates on its parts (with unequal rates even a
+//    uniform fluid at rest is unstable).  The forcing of eq. GGi enters in
+//    moment space with (I - S/2) in place of the scalar (1 - 1/(2 tau_g)).
+//    With every rate equal this is BGK.
 //
 // The scalar type is a template parameter.  With R = double this is the
 // oracle; with R = Dual (value + one tangent) the same code, unchanged, is
@@ -112,6 +124,32 @@ int opposite(int i) {
   return -1;
 }
 
+// Orthogonal D2Q9 moment basis (Lallemand and Luo, Phys. Rev. E 61, 6546),
+// evaluated from its defining polynomials of the lattice velocity c:
+//   1, e = 3|c|^2 - 4, eps = (9|c|^4 - 21|c|^2 + 8)/2, j_x = c_x,
+//   q_x = (3|c|^2 - 5) c_x, j_y = c_y, q_y = (3|c|^2 - 5) c_y,
+//   p_xx = c_x^2 - c_y^2, p_xy = c_x c_y.
+// The rows are orthogonal, so the inverse is the transpose divided by the
+// squared row norms.
+struct MomentBasis {
+  double M[Q][Q];  // [moment][direction]
+  double norm2[Q];
+  MomentBasis() {
+    for (int i = 0; i < Q; ++i) {
+      const double cx = CX[i], cy = CY[i], c2 = cx * cx + cy * cy;
+      const double row[Q] = {1.0, 3.0 * c2 - 4.0, (9.0 * c2 * c2 - 21.0 * c2 + 8.0) / 2.0,
+                             cx, (3.0 * c2 - 5.0) * cx, cy, (3.0 * c2 - 5.0) * cy,
+                             cx * cx - cy * cy, cx * cy};
+      for (int k = 0; k < Q; ++k) M[k][i] = row[k];
+    }
+    for (int k = 0; k < Q; ++k) {
+      norm2[k] = 0.0;
+      for (int i = 0; i < Q; ++i) norm2[k] += M[k][i] * M[k][i];
+    }
+  }
+};
+const MomentBasis MB;
+
 }  // namespace
 
 extern "C" {
@@ -120,6 +158,8 @@ extern "C" {
 enum { ORC_PERIODIC = 0, ORC_WALL = 1 };
 // Viscosity across the interface: nu, 1/nu or ln nu linear in phi.
 enum { ORC_NU_LINEAR = 0, ORC_NU_INVERSE = 1, ORC_NU_EXP = 2 };
+// Collision operator.
+enum { ORC_BGK = 0, ORC_MRT = 1 };
 
 typedef struct {
   int32_t nx, ny;
@@ -131,6 +171,9 @@ typedef struct {
   double M, alpha;      // tau_f = 1/2 + M/(c_s^2 alpha)
   double gx, gy;        // body force G
   int32_t nu_form;      // ORC_NU_*
+  int32_t collision;    // ORC_BGK or ORC_MRT
+  double mrt_f[4];      // MRT rates of f for e, eps, q, p (p_xx and p_xy)
+  double mrt_g[2];      // MRT rates of g for (rho, e, eps) together, and q
 } orc_params;
 
 }  // extern "C"
@@ -264,15 +307,35 @@ struct Sim {
       out[i] = (i == 0 ? pp * INV_CS2 * (WT[0] - 1.0) : pp * INV_CS2 * WT[i]) + rh * s_i(i, vx, vy);
   }
   // Sec. 2.3.2, eq. GGi (reading of the unbalanced parenthesis: the third
-  // term is the dyad u grad(rho) contracted with c_i c_i - c_s^2 I, over c_s^2).
-  void forcing(R tau, R vx, R vy, R fx, R fy, R rx, R ry, R* out) const {
+  // term is the dyad u grad(rho) contracted with c_i c_i - c_s^2 I, over c_s^2),
+  // times the prefactor k: 1 - 1/(2 tau_g) for BGK, 1 for MRT (which applies
+  // its prefactor per moment).
+  void forcing(R k, R vx, R vy, R fx, R fy, R rx, R ry, R* out) const {
     R ugr = vx * rx + vy * ry;
     for (int i = 0; i < Q; ++i) {
       R cF = CX[i] * fx + CY[i] * fy;
       // (u grad rho) : (c c - c_s^2 I) = sum_ab u_a d_b rho (c_a c_b - c_s^2 delta_ab)
       R dyad = vx * rx * (CX[i] * CX[i] - CS2) + vx * ry * (CX[i] * CY[i]) +
                vy * rx * (CY[i] * CX[i]) + vy * ry * (CY[i] * CY[i] - CS2);
-      out[i] = (1.0 - 1.0 / (2.0 * tau)) * WT[i] * (ugr + cF * INV_CS2 + dyad * INV_CS2);
+      out[i] = k * WT[i] * (ugr + cF * INV_CS2 + dyad * INV_CS2);
+    }
+  }
+  // MRT: out_i = sum_k Minv[i][k] (rate_k m_k + pre_k n_k) with m = M a and
+  // n = M b, i.e. the relaxation of a (rates) plus the forcing b (prefactors).
+  static void mrt_apply(const R* rate, const R* pre, const R* a, const R* b, R* out) {
+    R mk[Q];
+    for (int k = 0; k < Q; ++k) {
+      R ma = 0.0, mb = 0.0;
+      for (int i = 0; i < Q; ++i) {
+        ma += MB.M[k][i] * a[i];
+        mb += MB.M[k][i] * b[i];
+      }
+      mk[k] = rate[k] * ma + pre[k] * mb;
+    }
+    for (int i = 0; i < Q; ++i) {
+      R v = 0.0;
+      for (int k = 0; k < Q; ++k) v += MB.M[k][i] / MB.norm2[k] * mk[k];
+      out[i] = v;
     }
   }
   // Sec. 2.3.2, macroscopic subequations: u and p from g, rho, F, grad(rho).
@@ -324,18 +387,42 @@ struct Sim {
       feq(phi[k], mu[k], eq);
       source(S[k], Fn);
       source(Sp[k], Fo);
-      for (int i = 0; i < Q; ++i) {
-        R fi = f[i * n + k];
-        // eq. BGK with delta_t = 1 and dF/dt ~ F(t) - F(t-1)
-        fs[i * n + k] = fi - omega_f * (fi - eq[i]) + Fn[i] + 0.5 * (Fn[i] - Fo[i]);
-      }
       R tau_g = 0.5 + nu[k] * INV_CS2;  // viscosity-relaxation relation, solved for tau_g
       R omega_g = 1.0 / tau_g;
       geq(pr[k], rho[k], ux[k], uy[k], ge);
-      forcing(tau_g, ux[k], uy[k], Fx[k], Fy[k], grhx[k], grhy[k], Gi);
-      for (int i = 0; i < Q; ++i) {
-        R gi = g[i * n + k];
-        gs[i * n + k] = gi - omega_g * (gi - ge[i]) + Gi[i];  // eq. BGK-NS
+      if (p.collision == ORC_BGK) {
+        for (int i = 0; i < Q; ++i) {
+          R fi = f[i * n + k];
+          // eq. BGK with delta_t = 1 and dF/dt ~ F(t) - F(t-1)
+          fs[i * n + k] = fi - omega_f * (fi - eq[i]) + Fn[i] + 0.5 * (Fn[i] - Fo[i]);
+        }
+        forcing(1.0 - 1.0 / (2.0 * tau_g), ux[k], uy[k], Fx[k], Fy[k], grhx[k], grhy[k], Gi);
+        for (int i = 0; i < Q; ++i) {
+          R gi = g[i * n + k];
+          gs[i * n + k] = gi - omega_g * (gi - ge[i]) + Gi[i];  // eq. BGK-NS
+        }
+      } else if (p.collision == ORC_MRT) {
+        // moment order: rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy
+        const R rf[Q] = {omega_f, p.mrt_f[0], p.mrt_f[1], omega_f, p.mrt_f[2],
+                         omega_f, p.mrt_f[2], p.mrt_f[3], p.mrt_f[3]};
+        const R rg[Q] = {p.mrt_g[0], p.mrt_g[0], p.mrt_g[0], omega_g, p.mrt_g[1],
+                         omega_g, p.mrt_g[1], omega_g, omega_g};
+        R zero[Q], pre_f[Q], pre_g[Q], df[Q], dg[Q], rel[Q];
+        for (int q = 0; q < Q; ++q) {
+          zero[q] = 0.0;
+          pre_f[q] = 0.0;
+          pre_g[q] = 1.0 - 0.5 * rg[q];
+          df[q] = eq[q] - f[q * n + k];
+          dg[q] = ge[q] - g[q * n + k];
+        }
+        mrt_apply(rf, pre_f, df, zero, rel);
+        for (int i = 0; i < Q; ++i)
+          fs[i * n + k] = f[i * n + k] + rel[i] + Fn[i] + 0.5 * (Fn[i] - Fo[i]);
+        forcing(R(1.0), ux[k], uy[k], Fx[k], Fy[k], grhx[k], grhy[k], Gi);
+        mrt_apply(rg, pre_g, dg, Gi, rel);
+        for (int i = 0; i < Q; ++i) gs[i * n + k] = g[i * n + k] + rel[i];
+      } else {
+        std::abort();
       }
     }
   }
@@ -439,7 +526,7 @@ void orc_geq(const orc_params* p, double pr, double rho, double ux, double uy, d
 }
 void orc_forcing(const orc_params* p, double tau, double ux, double uy, double Fx, double Fy,
                  double rx, double ry, double* out) {
-  Sim<double> s(*p); s.forcing(tau, ux, uy, Fx, Fy, rx, ry, out);
+  Sim<double> s(*p); s.forcing(1.0 - 1.0 / (2.0 * tau), ux, uy, Fx, Fy, rx, ry, out);
 }
 void orc_macro(const orc_params* p, const double* g9, double rho, double Fx, double Fy,
                double rx, double ry, double* ux, double* uy, double* pr) {

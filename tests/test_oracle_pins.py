@@ -197,6 +197,96 @@ def test_well_balanced_fixed_point(shape, bcx):
         assert np.abs(m["mu"] - mu0).max() <= 1e-15
 
 
+# MRT rates of the free moments used by the pins below: f (e, eps, q, p), g
+# ((rho, e, eps) together, q); all away from the BGK rates of the workloads.
+MRT_F = (1.3, 1.1, 1.6, 1.4)
+MRT_G = (1.5, 1.7)
+
+
+@pytest.mark.parametrize("shape,bcx", [("flat", 1), ("drop", 0), ("drop", 1)])
+def test_mrt_keeps_the_well_balanced_fixed_point(shape, bcx):
+    # The discrete equilibrium has f = f^eq, zero source and a force whose
+    # forcing term lives in the momentum moments only, which MRT relaxes at
+    # the BGK rate: it stays a fixed point whatever the other rates are.
+    prm, ps, mu0 = _wb_state(shape, bcx)
+    prm.collision, prm.mrt_f, prm.mrt_g = oracle.MRT, MRT_F, MRT_G
+    s = oracle.Sim(prm).init(ps)
+    s.step(300)
+    m = s.moments()
+    assert np.hypot(m["ux"], m["uy"]).max() <= 1e-14
+    assert np.abs(m["phi"] - ps).max() <= 1e-12
+    assert np.abs(m["mu"] - mu0).max() <= 1e-15
+
+
+def test_mrt_with_equal_rates_is_bgk():
+    # With every moment relaxed at the BGK rate the moment-space collision is
+    # M^-1 (w I) M = w I: the same step to rounding (uniform tau_g needs
+    # nu_A = nu_B).
+    wl = inputs.Workload("mrt_eq", 24, 20, bc_x=1, rho_A=10.0, rho_B=1.0, nu_A=0.07, nu_B=0.07,
+                         sigma=5e-3, W=4.0, M=0.05, alpha=0.8)
+    phi0 = inputs.two_drops(24, 20, 5.0, 4.0, noise=1e-3)
+    a = oracle.Sim(oracle.params_for(wl, gx=1e-6)).init(phi0).step(60)
+    prm = oracle.params_for(wl, gx=1e-6)
+    wf, wg = 1.0 / prm.tau_f, 1.0 / (0.5 + 3.0 * 0.07)
+    prm.collision, prm.mrt_f, prm.mrt_g = oracle.MRT, (wf,) * 4, (wg,) * 2
+    b = oracle.Sim(prm).init(phi0).step(60)
+    for x, y in zip(a.get_state(), b.get_state()):
+        assert np.abs(x - y).max() <= 1e-13 * np.abs(x).max()
+    assert np.abs(a.moments()["ux"]).max() > 1e-7
+
+
+def _moment_vectors():
+    # population-space vectors v_k with M v_k = e_k for the orthogonal
+    # moment basis (1, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy)
+    c2 = CX ** 2 + CY ** 2
+    rows = np.array([np.ones(9), 3 * c2 - 4, (9 * c2 ** 2 - 21 * c2 + 8) / 2, CX, (3 * c2 - 5) * CX,
+                     CY, (3 * c2 - 5) * CY, CX ** 2 - CY ** 2, CX * CY], dtype=float)
+    assert np.allclose(rows @ rows.T, np.diag(np.diag(rows @ rows.T)))
+    return rows / (rows ** 2).sum(1)[:, None]
+
+
+def test_mrt_uniform_fluid_is_stable():
+    # A uniform fluid at rest with a random perturbation of g stays bounded
+    # for pressure-moment and q rates across (0, 2) (the reason the rho, e and
+    # eps moments of g share one rate).
+    rng = np.random.default_rng(0)
+    n = 12
+    for rates in [(0.7, 1.9), (1.5, 1.5), (1.9, 1.0), (1.99, 1.99)]:
+        prm = oracle.Params(nx=n, ny=n, kappa=1e-3, beta=1e-3, nu_A=0.1, nu_B=0.1, M=0.1,
+                            collision=oracle.MRT, mrt_f=(1.0,) * 4, mrt_g=rates)
+        s = oracle.Sim(prm).init(np.ones((n, n)))
+        f, g, Sp = s.get_state()
+        s.set_state(f, g + 1e-6 * rng.standard_normal(g.shape), Sp)
+        s.step(1000)
+        assert np.abs(s.get_state()[1]).max() < 1e-5, rates
+
+
+def test_mrt_relaxes_each_moment_at_its_rate():
+    # On one periodic cell every gradient vanishes and streaming returns each
+    # population to the cell.  At phi = (phi_A + phi_B)/2, mu = 0, so f^eq = 0
+    # and, with p = u = 0, g^eq = 0: a perturbation along one moment comes
+    # back after one step scaled by (1 - its rate) and nothing else.
+    prm = oracle.Params(nx=1, ny=1, kappa=1e-3, beta=1e-3, M=0.1, alpha=1.0, nu_A=0.1, nu_B=0.1,
+                        collision=oracle.MRT, mrt_f=MRT_F, mrt_g=MRT_G)
+    wf, wg = 1.0 / prm.tau_f, 1.0 / 0.8
+    rate_f = [None, MRT_F[0], MRT_F[1], wf, MRT_F[2], wf, MRT_F[2], MRT_F[3], MRT_F[3]]
+    rate_g = {4: MRT_G[1], 6: MRT_G[1], 7: wg, 8: wg}  # moments that leave p and u alone
+    V = _moment_vectors()
+    zero = np.zeros((9, 1, 1))
+    for k in range(1, 9):
+        v = 1e-3 * V[k][:, None, None]
+        s = oracle.Sim(prm).set_state(v, zero, np.zeros((1, 1)))
+        f, g, _ = s.step(1).get_state()
+        assert np.abs(f - (1 - rate_f[k]) * v).max() <= 1e-18, k
+        assert np.abs(g).max() == 0.0
+    for k, r in rate_g.items():
+        v = 1e-3 * V[k][:, None, None]
+        s = oracle.Sim(prm).set_state(zero, v, np.zeros((1, 1)))
+        f, g, _ = s.step(1).get_state()
+        assert np.abs(g - (1 - r) * v).max() <= 1e-18, k
+        assert np.abs(f).max() == 0.0
+
+
 def test_flat_interface_relaxes_to_discrete_equilibrium():
     # Flat interface, 256 x 4, walls in x, 20000 steps: phi departs from
     # the continuum tanh by the lattice's discrete equilibrium offset
@@ -263,12 +353,15 @@ def test_laplace_law():
     assert 0.97 <= ratio <= 1.02, ratio
 
 
+@pytest.mark.parametrize("collision", [oracle.BGK, oracle.MRT])
 @pytest.mark.parametrize("phase", [1.0, -1.0])
-def test_uniform_body_force_momentum(phase):
+def test_uniform_body_force_momentum(phase, collision):
     # Guo-type forcing: with g = 0 initially and a uniform body force G,
     # momentum grows by G per step and rho u = (t + 1/2) G exactly
-    # (Sec. 2.3.2, eq. GGi and the rho u = sum c g + F/2 recovery).
-    prm = oracle.Params(nx=8, ny=6, rho_A=3.0, rho_B=1.5, gx=1e-5, gy=-2e-5)
+    # (Sec. 2.3.2, eq. GGi and the rho u = sum c g + F/2 recovery); under
+    # MRT as well, whose (I - S/2) forcing leaves the momentum gain at G.
+    prm = oracle.Params(nx=8, ny=6, rho_A=3.0, rho_B=1.5, gx=1e-5, gy=-2e-5, collision=collision,
+                        mrt_f=MRT_F, mrt_g=MRT_G)
     s = oracle.Sim(prm).init(np.full((6, 8), phase))
     s.step(37)
     m = s.moments()
@@ -297,19 +390,23 @@ def test_shear_wave_decay(phase):
     assert rate == pytest.approx(nu * k * k, rel=5e-3)
 
 
+@pytest.mark.parametrize("collision", [oracle.BGK, oracle.MRT])
 @pytest.mark.parametrize("form", [oracle.NU_LINEAR, oracle.NU_INVERSE, oracle.NU_EXP])
 @pytest.mark.parametrize("s_A", [0.0, 0.25, 0.5, 1.0])
-def test_shear_wave_decay_viscosity_forms(form, s_A):
+def test_shear_wave_decay_viscosity_forms(form, s_A, collision):
     # A uniform phi is a fixed point of the order-parameter update (grad phi,
     # grad mu and the source all vanish), so a transverse wave in it decays at
     # nu(phi) k^2.  With s_A the phase-A fraction, the three forms of Sec. 2.3.2
     # make nu the weighted arithmetic, harmonic and geometric mean of nu_A and
     # nu_B; between the phases they differ by up to a factor of three here.
+    # Under MRT only the stress moments set the shear viscosity: the same
+    # rates hold with the other moments relaxed at unrelated rates.
     nx, ny = 64, 2
     k = 2 * np.pi / nx
     nu_A, nu_B = 0.02, 0.2
     prm = oracle.Params(nx=nx, ny=ny, rho_A=3.0, rho_B=1.0, nu_A=nu_A, nu_B=nu_B,
-                        kappa=1e-3, beta=1e-3, nu_form=form)
+                        kappa=1e-3, beta=1e-3, nu_form=form, collision=collision, mrt_f=MRT_F,
+                        mrt_g=MRT_G)
     phi = -1.0 + 2.0 * s_A
     X = np.broadcast_to(np.arange(nx, dtype=float), (ny, nx))
     s = oracle.Sim(prm).init(np.full((ny, nx), phi), None, 1e-6 * np.sin(k * X))
@@ -348,7 +445,8 @@ def test_sound_wave_speed():
     assert period == pytest.approx(2 * np.pi / (np.sqrt((1 / 3) / (1 - 4 / 9)) * k), rel=5e-3)
 
 
-def test_linear_cahn_hilliard_decay():
+@pytest.mark.parametrize("collision", [oracle.BGK, oracle.MRT])
+def test_linear_cahn_hilliard_decay(collision):
     # Recovered CH equation (Sec. 2.3.1, eq. CH_equation3) with
     # M = c_s^2 alpha (tau_f - 1/2) (eq. mobility): a small perturbation of the
     # bulk phase A decays at M k^2 (psi''(phi_A) + kappa k^2), psi'' = 8 beta
@@ -356,7 +454,9 @@ def test_linear_cahn_hilliard_decay():
     nx, ny = 64, 4
     k = 2 * np.pi / nx
     kappa, beta, M = 0.04, 0.005, 0.1
-    prm = oracle.Params(nx=nx, ny=ny, kappa=kappa, beta=beta, M=M, alpha=0.7)
+    # Under MRT the mobility is set by the flux moments alone.
+    prm = oracle.Params(nx=nx, ny=ny, kappa=kappa, beta=beta, M=M, alpha=0.7, collision=collision,
+                        mrt_f=MRT_F, mrt_g=MRT_G)
     X = np.broadcast_to(np.arange(nx, dtype=float), (ny, nx))
     s = oracle.Sim(prm).init(1.0 + 1e-6 * np.sin(k * X))
     amp = []
@@ -409,14 +509,16 @@ def test_mirror_symmetry_with_walls():
     assert np.abs(m["ux"]).max() > 1e-9
 
 
-@pytest.mark.parametrize("form,nu_A,nu_B", [(oracle.NU_LINEAR, 0.1, 0.1), (oracle.NU_LINEAR, 0.05, 0.2),
-                                             (oracle.NU_INVERSE, 0.05, 0.2), (oracle.NU_EXP, 0.05, 0.2)])
-def test_tlm_matches_central_differences(form, nu_A, nu_B):
+@pytest.mark.parametrize("form,nu_A,nu_B,coll", [
+    (oracle.NU_LINEAR, 0.1, 0.1, oracle.BGK), (oracle.NU_LINEAR, 0.05, 0.2, oracle.BGK),
+    (oracle.NU_INVERSE, 0.05, 0.2, oracle.BGK), (oracle.NU_EXP, 0.05, 0.2, oracle.BGK),
+    (oracle.NU_LINEAR, 0.05, 0.2, oracle.MRT), (oracle.NU_EXP, 0.05, 0.2, oracle.MRT)])
+def test_tlm_matches_central_differences(form, nu_A, nu_B, coll):
     # The dual-number instantiation is the exact tangent of the FP64 step;
     # check it against central differences of the plain oracle.
     rng = np.random.default_rng(5)
     prm = oracle.params_for(inputs.ADJOINT, nx=16, ny=12, bc_x=oracle.WALL, nu_form=form,
-                            nu_A=nu_A, nu_B=nu_B)
+                            nu_A=nu_A, nu_B=nu_B, collision=coll, mrt_f=MRT_F, mrt_g=MRT_G)
     phi0 = inputs.two_drops(16, 12, 3.0, 4.0, noise=1e-2)
     s = oracle.Sim(prm).init(phi0).step(3)
     f, g, Sp = s.get_state()
