@@ -55,6 +55,9 @@ enum { LBM_PERIODIC = 0, LBM_WALL = 1 };
 /* Viscosity across the interface (lbm_params.nu_form). */
 enum { LBM_NU_LINEAR = 0, LBM_NU_INVERSE = 1, LBM_NU_EXP = 2 };
 
+/* Collision operator (lbm_params.collision). */
+enum { LBM_BGK = 0, LBM_MRT = 1 };
+
 /*
  * Problem parameters, in the paper's notation.
  *   phi_A, phi_B   order parameter of the two bulk phases (Sec. 2.1, eq. bulk_energy).
@@ -97,6 +100,22 @@ enum { LBM_NU_LINEAR = 0, LBM_NU_INVERSE = 1, LBM_NU_EXP = 2 };
  *                  s = -nu_A/(nu_B - nu_A) when nu_A < nu_B (and mirrored),
  *                  so the inverse form needs phi to stay that close to the
  *                  bulk values.
+ *   collision      LBM_BGK: single relaxation time for both populations, as
+ *                  in the paper (eqs. BGK, BGK-NS).
+ *                  LBM_MRT: multiple relaxation times, the extension the paper
+ *                  names (Sec. 2.3) without giving it: the non-equilibrium
+ *                  part is relaxed in the orthogonal D2Q9 moment basis of
+ *                  Lallemand and Luo, m = (rho, e, eps, j_x, q_x, j_y, q_y,
+ *                  p_xx, p_xy).  f: phi and j at 1/tau_f (the mobility is
+ *                  unchanged), e, eps, q, (p_xx, p_xy) at mrt_f[0..3]; the
+ *                  source is added as in BGK.  g: j, p_xx, p_xy at
+ *                  1/tau_g(phi) (the viscosity is unchanged), (rho, e, eps)
+ *                  together at mrt_g[0], q at mrt_g[1]; the forcing of eq.
+ *                  GGi enters as M^-1 (I - S/2) M G~.  rho, e and eps of g
+ *                  share one rate because p is recovered from
+ *                  sum_{i!=0} g_i = (8 rho + e - eps)/9.  Every rate must lie
+ *                  in (0, 2); with all rates equal to the BGK ones the result
+ *                  is the BGK step.
  */
 typedef struct lbm_params {
   int32_t nx, ny;
@@ -113,6 +132,9 @@ typedef struct lbm_params {
   int32_t diag_every;
   int32_t kernel_path;
   int32_t nu_form;
+  int32_t collision;
+  double mrt_f[4];
+  double mrt_g[2];
 } lbm_params;
 
 /* Derived constants (lattice units). */
@@ -149,7 +171,8 @@ typedef struct lbm_ctx lbm_ctx;
  * than 2^31 - 1 cells; bc not 0/1; precision not 32/64; phi_A == phi_B;
  * rho_A, rho_B <= 0; nu_A, nu_B <= 0; M <= 0; alpha <= 0; kappa or beta
  * < 0 (or sigma, W <= 0 with use_sigma_W); diag_every < 0; kernel_path not
- * 0..2; nu_form not one of LBM_NU_*. */
+ * 0..2; nu_form not one of LBM_NU_*; collision not LBM_BGK or LBM_MRT; with
+ * LBM_MRT, an MRT rate outside (0, 2). */
 int lbm_derive(const lbm_params* p, lbm_derived* out);
 
 /* Bytes the caller must allocate for the state and the workspace (0 if `p`

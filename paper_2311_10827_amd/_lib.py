@@ -39,7 +39,8 @@ class LbmParams(ctypes.Structure):
         ("M", ctypes.c_double), ("alpha", ctypes.c_double),
         ("gx", ctypes.c_double), ("gy", ctypes.c_double),
         ("diag_every", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
-        ("nu_form", ctypes.c_int32),
+        ("nu_form", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("mrt_f", ctypes.c_double * 4), ("mrt_g", ctypes.c_double * 2),
     ]
 
 

@@ -74,7 +74,84 @@ struct KP {
   double nuA, ln_nuA, ln_nuB;   // for the inverse-linear and exponential forms
   double nu_dphi;               // d nu/d phi over nu^2 (inverse) or over nu (exponential)
   double inv_nuA, inv_nuB;      // 1/nu_A, 1/nu_B
+  int collision;                // 0 BGK, 1 MRT
+  double mf[4];                 // MRT rates of f: e, eps, q, p
+  double mg[2];                 // MRT rates of g: (rho, e, eps), q
 };
+
+// ---------------------------------------------------------------- MRT basis
+// Orthogonal D2Q9 moment basis of Lallemand and Luo,
+// m = (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy) = M v, from the
+// polynomials 1, 3|c|^2 - 4, (9|c|^4 - 21|c|^2 + 8)/2, c_x, (3|c|^2 - 5) c_x,
+// c_y, (3|c|^2 - 5) c_y, c_x^2 - c_y^2, c_x c_y of the lattice velocities.
+template <typename C>
+__device__ __forceinline__ void mom_fwd(const C (&v)[9], C (&m)[9]) {
+  const C a = (v[1] + v[2]) + (v[3] + v[4]);  // axis links
+  const C d = (v[5] + v[6]) + (v[7] + v[8]);  // diagonal links
+  m[0] = v[0] + a + d;
+  m[1] = C(-4) * v[0] - a + C(2) * d;
+  m[2] = C(4) * v[0] - C(2) * a + d;
+  const C jxa = v[1] - v[3], jxd = (v[5] - v[6]) + (v[8] - v[7]);
+  const C jya = v[2] - v[4], jyd = (v[5] + v[6]) - (v[7] + v[8]);
+  m[3] = jxa + jxd;
+  m[4] = C(-2) * jxa + jxd;
+  m[5] = jya + jyd;
+  m[6] = C(-2) * jya + jyd;
+  m[7] = (v[1] + v[3]) - (v[2] + v[4]);
+  m[8] = (v[5] + v[7]) - (v[6] + v[8]);
+}
+// v = M^-1 m = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4) m
+// (the rows of M are orthogonal with those squared norms).
+template <typename C>
+__device__ __forceinline__ void mom_inv(const C (&m)[9], C (&v)[9]) {
+  const C r = m[0] * C(1.0 / 9), e = m[1] * C(1.0 / 36), ep = m[2] * C(1.0 / 36);
+  const C jx = m[3] * C(1.0 / 6), qx = m[4] * C(1.0 / 12), jy = m[5] * C(1.0 / 6),
+          qy = m[6] * C(1.0 / 12), pxx = m[7] * C(0.25), pxy = m[8] * C(0.25);
+  v[0] = r - C(4) * e + C(4) * ep;
+  const C ax = r - e - C(2) * ep, dg = r + C(2) * e + ep;
+  const C hx = jx - C(2) * qx, hy = jy - C(2) * qy;  // axis: j - 2q
+  const C sx = jx + qx, sy = jy + qy;                // diagonal: j + q
+  v[1] = ax + hx + pxx;
+  v[2] = ax + hy - pxx;
+  v[3] = ax - hx + pxx;
+  v[4] = ax - hy - pxx;
+  v[5] = dg + sx + sy + pxy;
+  v[6] = dg - sx + sy - pxy;
+  v[7] = dg - sx - sy + pxy;
+  v[8] = dg + sx - sy - pxy;
+}
+// MRT relaxation: out = M^-1 (rate * (M d) + pre * (M b)) per moment; b may
+// be all zero (then pass has_b = false).
+template <typename C, bool HAS_B>
+__device__ __forceinline__ void mrt_relax(const C (&rate)[9], const C (&d)[9], const C (&b)[9],
+                                          C (&out)[9]) {
+  C md[9], m[9];
+  mom_fwd(d, md);
+  if constexpr (HAS_B) {
+    C mb[9];
+    mom_fwd(b, mb);
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = rate[k] * md[k] + (C(1) - C(0.5) * rate[k]) * mb[k];
+  } else {
+#pragma unroll
+    for (int k = 0; k < 9; ++k) m[k] = rate[k] * md[k];
+  }
+  mom_inv(m, out);
+}
+// Rates per moment (rho, e, eps, j_x, q_x, j_y, q_y, p_xx, p_xy).  f: the
+// fluxes (and the conserved phi) at 1/tau_f; g: the fluxes and stresses at
+// 1/tau_g, rho, e and eps at one common rate (p is recovered from
+// sum_{i!=0} g_i = (8 rho + e - eps)/9, which unequal rates would disturb).
+template <typename C>
+__device__ __forceinline__ void mrt_rates_f(const KP& p, C wf, C (&r)[9]) {
+  r[0] = wf; r[1] = C(p.mf[0]); r[2] = C(p.mf[1]); r[3] = wf; r[4] = C(p.mf[2]);
+  r[5] = wf; r[6] = C(p.mf[2]); r[7] = C(p.mf[3]); r[8] = C(p.mf[3]);
+}
+template <typename C>
+__device__ __forceinline__ void mrt_rates_g(const KP& p, C wg, C (&r)[9]) {
+  r[0] = C(p.mg[0]); r[1] = C(p.mg[0]); r[2] = C(p.mg[0]); r[3] = wg; r[4] = C(p.mg[1]);
+  r[5] = wg; r[6] = C(p.mg[1]); r[7] = wg; r[8] = wg;
+}
 
 // Viscosity across the interface (Sec. 2.3.2).  The paper adopts nu linear in
 // phi (eq. vis); it names the inverse-linear and the exponential forms as the

@@ -194,8 +194,9 @@ struct CellOut {
 };
 
 // FP64 cell update, plain-definition order.  Writes the post-collision
-// populations to fo/go when WRITE is set.
-template <bool WRITE>
+// populations to fo/go when WRITE is set; MRT selects the moment-space
+// collision in place of BGK.
+template <bool WRITE, bool MRT = false>
 __device__ __forceinline__ void cell_f64(const KP& p, const Pops<double>& q, const Nbhd<double>& n,
                                          double Sp, double (&fo)[9], double (&go)[9], CellOut& out) {
   double rho3[3][3];
@@ -227,18 +228,34 @@ __device__ __forceinline__ void cell_f64(const KP& p, const Pops<double>& q, con
   if (!WRITE) return;
   // order-parameter population (Sec. 2.3.1, eqs. BGK, H_i, F_i)
   const double* f = q.f;
+  if constexpr (MRT) {
+    double d[9], rel[9], rate[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const double feq = i == 0 ? phi - ((1.0 - w_of(0)) * p.alpha) * mu : (w_of(i) * p.alpha) * mu;
-    const double Fn = (w_of(i) * S) * src_bracket(i);
-    const double Fo = (w_of(i) * Sp) * src_bracket(i);
-    fo[i] = ((f[i] - p.omega_f * (f[i] - feq)) + Fn) + 0.5 * (Fn - Fo);
+    for (int i = 0; i < 9; ++i)
+      d[i] = (i == 0 ? phi - ((1.0 - w_of(0)) * p.alpha) * mu : (w_of(i) * p.alpha) * mu) - f[i];
+    mrt_rates_f(p, p.omega_f, rate);
+    mrt_relax<double, false>(rate, d, d, rel);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const double Fn = (w_of(i) * S) * src_bracket(i);
+      const double Fo = (w_of(i) * Sp) * src_bracket(i);
+      fo[i] = ((f[i] + rel[i]) + Fn) + 0.5 * (Fn - Fo);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const double feq = i == 0 ? phi - ((1.0 - w_of(0)) * p.alpha) * mu : (w_of(i) * p.alpha) * mu;
+      const double Fn = (w_of(i) * S) * src_bracket(i);
+      const double Fo = (w_of(i) * Sp) * src_bracket(i);
+      fo[i] = ((f[i] - p.omega_f * (f[i] - feq)) + Fn) + 0.5 * (Fn - Fo);
+    }
   }
   // hydrodynamic population (Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi)
   const double tau = 0.5 + nu * INV_CS2;
   const double wg = 1.0 / tau;
-  const double kG = 1.0 - 1.0 / (2.0 * tau);
+  const double kG = MRT ? 1.0 : 1.0 - 1.0 / (2.0 * tau);  // MRT applies (I - S/2) per moment
   const double ugr = ux * grx + uy * gry;
+  double dg[9], Gt[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double cx = cx_of(i), cy = cy_of(i);
@@ -250,12 +267,24 @@ __device__ __forceinline__ void cell_f64(const KP& p, const Pops<double>& q, con
     const double d = (double)(cy_of(i) * cy_of(i)) - CS2;
     const double dyad = (((ux * grx) * a + (ux * gry) * b) + (uy * grx) * b) + (uy * gry) * d;
     const double Gi = (kG * w_of(i)) * ((ugr + cF * INV_CS2) + dyad * INV_CS2);
-    go[i] = (g[i] - wg * (g[i] - geq)) + Gi;
+    if constexpr (MRT) {
+      dg[i] = geq - g[i];
+      Gt[i] = Gi;
+    } else {
+      go[i] = (g[i] - wg * (g[i] - geq)) + Gi;
+    }
+  }
+  if constexpr (MRT) {
+    double rate[9], rel[9];
+    mrt_rates_g(p, wg, rate);
+    mrt_relax<double, true>(rate, dg, Gt, rel);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) go[i] = g[i] + rel[i];
   }
 }
 
 // FP32 cell update in difference forms.  fo[0] receives hi, fo_lo the low word.
-template <bool WRITE>
+template <bool WRITE, bool MRT = false>
 __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, const Nbhd<float>& n,
                                          float Sp, float (&fo)[9], float& fo_lo, float (&go)[9],
                                          CellOut& out) {
@@ -300,19 +329,37 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
   const float am = (float)p.alpha * mu;
   // f_0 - f_0^eq = -(s8 - (5/9) alpha mu) exactly, since phi = f_0 + s8; add the
   // small increment to hi + lo (FastTwoSum keeps the rounding error in lo).
-  const float inc0 = wf * (s8 - (float)(5.0 / 9.0) * am) + (float)(w_of(0) * src_bracket(0)) * src;
+  float rel_f[9];  // MRT: M^-1 S M (f^eq - f)
+  if constexpr (MRT) {
+    // f^eq_0 - f_0 = s8 - (5/9) alpha mu exactly (phi = f_0 + s8)
+    float d[9], rate[9];
+    d[0] = s8 - (float)(5.0 / 9.0) * am;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) d[i] = (float)w_of(i) * am - f[i];
+    mrt_rates_f(p, wf, rate);
+    mrt_relax<float, false>(rate, d, d, rel_f);
+  }
+  const float inc0 = (MRT ? rel_f[0] : wf * (s8 - (float)(5.0 / 9.0) * am)) +
+                     (float)(w_of(0) * src_bracket(0)) * src;
   const float t = q.lo + inc0;
   const float hi = f[0] + t;
   fo[0] = hi;
   fo_lo = t - (hi - f[0]);
 #pragma unroll
   for (int i = 1; i < 9; ++i)
-    fo[i] = f[i] + wf * ((float)w_of(i) * am - f[i]) + (float)(w_of(i) * src_bracket(i)) * src;
+    fo[i] = f[i] + (MRT ? rel_f[i] : wf * ((float)w_of(i) * am - f[i])) +
+            (float)(w_of(i) * src_bracket(i)) * src;
   const float tau = 0.5f + 3.0f * visc<float>(p, dB);
   const float wg = 1.0f / tau;
-  const float kG = 1.0f - 0.5f * wg;
+  const float kG = MRT ? 1.0f : 1.0f - 0.5f * wg;  // MRT applies (I - S/2) per moment
   const float ge0 = -(float)(5.0 / 3.0) * pr - (float)(2.0 / 3.0) * rho * uu;
-  go[0] = g[0] + wg * (ge0 - g[0]);
+  float dg[9], Gt[9];
+  if constexpr (MRT) {
+    dg[0] = ge0 - g[0];
+    Gt[0] = 0.0f;  // G_0 vanishes: its u.grad(rho) terms cancel
+  } else {
+    go[0] = g[0] + wg * (ge0 - g[0]);
+  }
   const float p3 = 3.0f * pr, ruu = 1.5f * rho * uu;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
@@ -322,13 +369,25 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
     const float w = (float)w_of(i);
     const float geq = w * (p3 + rho * (cu * (3.0f + 4.5f * cu)) - ruu);
     const float Gi = kG * 3.0f * w * (cF + cu * cr);
-    go[i] = g[i] + wg * (geq - g[i]) + Gi;
+    if constexpr (MRT) {
+      dg[i] = geq - g[i];
+      Gt[i] = Gi;
+    } else {
+      go[i] = g[i] + wg * (geq - g[i]) + Gi;
+    }
+  }
+  if constexpr (MRT) {
+    float rate[9], rel[9];
+    mrt_rates_g(p, wg, rate);
+    mrt_relax<float, true>(rate, dg, Gt, rel);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) go[i] = g[i] + rel[i];
   }
 }
 
 // Spin holds S_prev of the current step; Spout receives S (they may be the
 // same plane: each cell reads and then writes only its own entry).
-template <typename T, int MODE>
+template <typename T, int MODE, bool MRT = false>
 __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bout, const T* Spin,
                                                   T* Spout, const T* __restrict__ dphi,
                                                   const T* __restrict__ mupl, MomOut mo,
@@ -352,9 +411,9 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
     T lo = 0;
     CellOut c;
     if constexpr (std::is_same<T, double>::value)
-      cell_f64<WRITE>(p, q, nb, Sp, fo, go, c);
+      cell_f64<WRITE, MRT>(p, q, nb, Sp, fo, go, c);
     else
-      cell_f32<WRITE>(p, q, nb, Sp, fo, lo, go, c);
+      cell_f32<WRITE, MRT>(p, q, nb, Sp, fo, lo, go, c);
     if (WRITE) {
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
@@ -440,7 +499,7 @@ __device__ __forceinline__ int mod_pos(int a, int m) {
   return r < 0 ? r + m : r;
 }
 
-template <typename T, int MODE, bool WRITE_PHIMU>
+template <typename T, int MODE, bool WRITE_PHIMU, bool MRT = false>
 __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T* Bin, T* Bout, const T* Spin,
                                                              T* Spout, T* __restrict__ dphi_out,
                                                              T* __restrict__ mu_out,
@@ -560,9 +619,9 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
         }
       }
       if constexpr (std::is_same<T, double>::value)
-        cell_f64<true>(p, q, nb, Sp, fo, go, c);
+        cell_f64<true, MRT>(p, q, nb, Sp, fo, go, c);
       else
-        cell_f32<true>(p, q, nb, Sp, fo, lo, go, c);
+        cell_f32<true, MRT>(p, q, nb, Sp, fo, lo, go, c);
     }
     // next row's loads go out before this row's stores
     if (y + 1 < y1) {

@@ -69,6 +69,11 @@ int validate(const lbm_params* p, lbm_derived* d) {
   if (p->diag_every < 0) return LBM_EINVAL;
   if (p->kernel_path < 0 || p->kernel_path > 2) return LBM_EINVAL;
   if (p->nu_form < LBM_NU_LINEAR || p->nu_form > LBM_NU_EXP) return LBM_EINVAL;
+  if (p->collision != LBM_BGK && p->collision != LBM_MRT) return LBM_EINVAL;
+  if (p->collision == LBM_MRT) {
+    for (double r : {p->mrt_f[0], p->mrt_f[1], p->mrt_f[2], p->mrt_f[3], p->mrt_g[0], p->mrt_g[1]})
+      if (!(r > 0.0 && r < 2.0)) return LBM_EINVAL;
+  }
   const size_t pitch = round_up((size_t)p->nx, 64);
   if (pitch * (size_t)p->ny > (size_t)INT32_MAX) return LBM_EINVAL;
   const double dphi = p->phi_A - p->phi_B;
@@ -189,12 +194,23 @@ int launch_phi_mu(lbm_ctx* c) {
   return launch_phi_mu<T>(c, popbuf<T>(c, c->cur));
 }
 
+// The collide-stream pass; the MRT instantiation for the modes that collide.
 template <typename T, int MODE>
-int launch_collide(lbm_ctx* c, MomOut mo, const T* Bin, T* Bout, const T* Sin, T* Sout) {
-  hipLaunchKernelGGL((k_collide<T, MODE>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream, c->kp, Bin,
-                     Bout, Sin, Sout, dphi_plane<T>(c), mu_plane<T>(c), mo, c->partials, c->ntx2);
+int launch_collide(lbm_ctx* c, MomOut mo, const T* Bin, T* Bout, const T* Sin, T* Sout, const T* dphi,
+                   const T* mu) {
+  constexpr bool COLLIDES = MODE == M_STEP || MODE == M_STEP_DIAG;
+  if (COLLIDES && c->kp.collision == LBM_MRT)
+    hipLaunchKernelGGL((k_collide<T, MODE, COLLIDES>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream,
+                       c->kp, Bin, Bout, Sin, Sout, dphi, mu, mo, c->partials, c->ntx2);
+  else
+    hipLaunchKernelGGL((k_collide<T, MODE>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream, c->kp,
+                       Bin, Bout, Sin, Sout, dphi, mu, mo, c->partials, c->ntx2);
   LAUNCHCHK(c);
   return LBM_OK;
+}
+template <typename T, int MODE>
+int launch_collide(lbm_ctx* c, MomOut mo, const T* Bin, T* Bout, const T* Sin, T* Sout) {
+  return launch_collide<T, MODE>(c, mo, Bin, Bout, Sin, Sout, dphi_plane<T>(c), mu_plane<T>(c));
 }
 template <typename T, int MODE>
 int launch_collide(lbm_ctx* c, MomOut mo) {
@@ -204,8 +220,13 @@ int launch_collide(lbm_ctx* c, MomOut mo) {
 
 template <typename T, int MODE, bool WRITE_PHIMU>
 int launch_fused(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
-  hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU>), dim3(c->ntxf * c->ntyf), dim3(Strip<T>::W), 0,
-                     c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf, c->hf);
+  if (c->kp.collision == LBM_MRT)
+    hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU, true>), dim3(c->ntxf * c->ntyf),
+                       dim3(Strip<T>::W), 0, c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials,
+                       c->ntxf, c->hf);
+  else
+    hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU>), dim3(c->ntxf * c->ntyf), dim3(Strip<T>::W),
+                       0, c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf, c->hf);
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -389,11 +410,8 @@ int step_into_impl(lbm_ctx* c, T* src, T* dst) {
   hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, src,
                      nullptr, snap_dphi(c, src), snap_mu(c, src), c->ntx1);
   LAUNCHCHK(c);
-  hipLaunchKernelGGL((k_collide<T, M_STEP>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream, c->kp, src,
-                     dst, snap_S(c, src), snap_S(c, dst), snap_dphi(c, src), snap_mu(c, src), MomOut{},
-                     c->partials, c->ntx2);
-  LAUNCHCHK(c);
-  return LBM_OK;
+  return launch_collide<T, M_STEP>(c, MomOut{}, src, dst, snap_S(c, src), snap_S(c, dst),
+                                  snap_dphi(c, src), snap_mu(c, src));
 }
 
 template <typename T>
@@ -570,6 +588,9 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   k.inv_nuB = 1.0 / p->nu_B;
   k.nu_dphi = p->nu_form == LBM_NU_INVERSE ? (k.inv_nuB - k.inv_nuA) / k.dphiAB
                                            : (k.ln_nuA - k.ln_nuB) / k.dphiAB;
+  k.collision = p->collision;
+  for (int i = 0; i < 4; ++i) k.mf[i] = p->mrt_f[i];
+  for (int i = 0; i < 2; ++i) k.mg[i] = p->mrt_g[i];
   hipError_t e = hipHostMalloc((void**)&c->diag_host, 2 * NQ * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
@@ -682,6 +703,10 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
 
 int lbm_adjoint_attach(lbm_ctx* c, void* adj_workspace) {
   if (!c || !adj_workspace || ((uintptr_t)adj_workspace & 255)) return LBM_EINVAL;
+  if (c->kp.collision != LBM_BGK) {
+    c->err = "lbm_adjoint_attach: the adjoint covers the BGK collision only";
+    return LBM_EINVAL;
+  }
   c->adj = static_cast<char*>(adj_workspace);
   c->th_part = reinterpret_cast<double*>(c->adj + ADJ_PLANES * adj_plane_bytes(&c->p));
   const long long tiles = (long long)c->ntx2 * c->nty2;

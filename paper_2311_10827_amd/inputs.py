@@ -169,6 +169,9 @@ class Workload:
     M: float = 0.05
     alpha: float = 1.0
     nu_form: int = 0       # 0 nu, 1 1/nu, 2 ln nu linear in phi
+    collision: int = 0     # 0 BGK, 1 MRT
+    mrt_f: tuple = (1.0, 1.0, 1.0, 1.0)  # MRT rates of f: e, eps, q, p
+    mrt_g: tuple = (1.0, 1.0)            # MRT rates of g: (rho, e, eps), q
     steps: int = 1000
     extra: dict = field(default_factory=dict)
 

@@ -15,6 +15,9 @@ from ._lib import LbmDiag, LbmParams, LbmDerived, check
 
 # viscosity across the interface (lbm_params.nu_form): nu, 1/nu or ln nu linear in phi
 NU_LINEAR, NU_INVERSE, NU_EXP = 0, 1, 2
+# collision operator (lbm_params.collision); MRT rates: mrt_f = f's (e, eps, q, p),
+# mrt_g = g's ((rho, e, eps), q)
+BGK, MRT = 0, 1
 
 
 def make_params(workload=None, precision: int = 64, diag_every: int = 0, **over) -> LbmParams:
@@ -26,15 +29,18 @@ def make_params(workload=None, precision: int = 64, diag_every: int = 0, **over)
     kw = dict(nx=0, ny=0, bc_x=0, bc_y=0, precision=precision, use_sigma_W=0, phi_A=1.0,
               phi_B=-1.0, rho_A=1.0, rho_B=1.0, nu_A=0.1, nu_B=0.1, kappa=0.0, beta=0.0,
               sigma=0.0, W=0.0, M=0.1, alpha=1.0, gx=0.0, gy=0.0, diag_every=diag_every,
-              kernel_path=0, nu_form=NU_LINEAR)
+              kernel_path=0, nu_form=NU_LINEAR, collision=BGK, mrt_f=(1.0, 1.0, 1.0, 1.0),
+              mrt_g=(1.0, 1.0))
     if workload is not None:
         for k in ("nx", "ny", "bc_x", "bc_y", "phi_A", "phi_B", "rho_A", "rho_B", "nu_A", "nu_B",
-                  "sigma", "W", "M", "alpha", "nu_form"):
+                  "sigma", "W", "M", "alpha", "nu_form", "collision", "mrt_f", "mrt_g"):
             kw[k] = getattr(workload, k)
         kw["use_sigma_W"] = 1
     if "kappa" in over or "beta" in over:
         kw["use_sigma_W"] = 0
     kw.update(over)
+    kw["mrt_f"] = (ctypes.c_double * 4)(*kw["mrt_f"])
+    kw["mrt_g"] = (ctypes.c_double * 2)(*kw["mrt_g"])
     return LbmParams(**kw)
 
 

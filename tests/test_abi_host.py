@@ -54,7 +54,8 @@ def test_derive_from_sigma_W():
     dict(rho_B=0.0), dict(rho_A=-2.0), dict(nu_A=0.0), dict(M=0.0), dict(alpha=0.0),
     dict(kappa=-1.0, beta=0.0), dict(diag_every=-1), dict(nx=65536, ny=65536),
     dict(gx=float("nan")), dict(kernel_path=3), dict(kernel_path=-1), dict(nu_form=3),
-    dict(nu_form=-1),
+    dict(nu_form=-1), dict(collision=2), dict(collision=1, mrt_f=(0.0, 1.0, 1.0, 1.0)),
+    dict(collision=1, mrt_g=(1.0, 2.0)), dict(collision=1, mrt_f=(1.0, 1.0, float("nan"), 1.0)),
 ])
 def test_derive_rejects(bad):
     p = make_params(inputs.FLAT, **bad)

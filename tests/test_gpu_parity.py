@@ -416,3 +416,52 @@ def test_viscosity_forms_against_oracle(form, path):
     assert d32["n_nonfinite"] == 0
     assert np.abs(m32["phi"] - om["phi"]).max() <= 1e-5
     assert max(np.abs(m32["ux"] - om["ux"]).max(), np.abs(m32["uy"] - om["uy"]).max()) <= 1e-6
+
+
+MRT_RATES = dict(collision=1, mrt_f=(1.3, 1.1, 1.6, 1.4), mrt_g=(1.5, 1.7))
+
+
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("case", ["walls_linear", "periodic_exp"])
+def test_mrt_against_oracle(case, path):
+    # The MRT collision (moment-space relaxation with rates away from BGK's)
+    # on a walled field with the linear viscosity law and on a periodic one
+    # with the exponential law: FP64 to 1e-12, FP32 within its bounds.
+    if case == "walls_linear":
+        wl = inputs.Workload("mrt_walls", 150, 70, bc_x=1, rho_A=10.0, rho_B=1.0, nu_A=0.02,
+                             nu_B=0.2, sigma=5e-3, W=4.0, M=0.05, **MRT_RATES)
+        phi0 = inputs.two_drops(150, 70, 16.0, 3.0, noise=1e-3, workload_id=12)
+    else:
+        wl = inputs.Workload("mrt_periodic", 131, 70, rho_A=100.0, rho_B=1.0, nu_A=0.01, nu_B=0.1,
+                             sigma=2e-3, W=4.0, M=0.05, nu_form=2, **MRT_RATES)
+        phi0 = inputs.two_drops(131, 70, 14.0, 3.0, noise=1e-3, workload_id=13)
+    say(f"[gpu] MRT {case}, kernel_path={path}")
+    o = oracle_sim(wl, phi0)
+    g64 = gpu_sim(wl, phi0, 64, kernel_path=path)
+    g32 = gpu_sim(wl, phi0, 32, kernel_path=path)
+    for n in (0, 1, 200):
+        o.step(n)
+        g64.step(n)
+        g32.step(n)
+        compare_state(gpu_state(g64), o.get_state(), TOL64)
+    om = o.moments()
+    assert np.abs(om["ux"]).max() > 1e-6
+    m32, d32 = gpu_moments(g32)
+    assert d32["n_nonfinite"] == 0
+    assert np.abs(m32["phi"] - om["phi"]).max() <= 1e-5
+    assert max(np.abs(m32["ux"] - om["ux"]).max(), np.abs(m32["uy"] - om["uy"]).max()) <= 1e-6
+
+
+@pytest.mark.parametrize("prec", [64, 32])
+def test_mrt_fused_and_two_kernel_paths_agree_bitwise(prec):
+    # 2100 x 1030 runs 32-row strips in the fused kernel
+    wl = inputs.Workload("mrt_big", 2100, 1030, bc_y=1, rho_A=10.0, rho_B=1.0, nu_A=0.02, nu_B=0.2,
+                         sigma=5e-3, W=4.0, M=0.05, **MRT_RATES)
+    phi0 = inputs.two_drops(2100, 1030, 200.0, 4.0, noise=1e-3, workload_id=14)
+    say(f"[gpu] MRT fused vs two-kernel, prec={prec}, 2100x1030")
+    a = gpu_sim(wl, phi0, prec, kernel_path=1)
+    b = gpu_sim(wl, phi0, prec, kernel_path=2)
+    a.step(30)
+    b.step(30)
+    for x, y in zip(gpu_state(a), gpu_state(b)):
+        assert np.array_equal(x, y)
