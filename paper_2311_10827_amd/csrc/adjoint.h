@@ -188,7 +188,7 @@ struct KaCell {
   T lphi, lmu, lgpx, lgpy, lgmx, lgmy;
 };
 
-template <typename T, bool INIT>
+template <typename T, bool INIT, bool MRT = false>
 __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, const T* __restrict__ dphi,
                                         const T* __restrict__ mupl, const T* __restrict__ lam_in, int x,
                                         int y, KaCell<T>& o, double (&th)[4]) {
@@ -265,16 +265,39 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   lS = uni(lam_in + 18 * n)[kd];  // S_prev(n+1) = S(n): no streaming
 
   // ---- order-parameter collision: f* = f - w_f (f - f^eq) + w b (3/2 S - 1/2 S_prev)
+  // (MRT: f* = f + R_f (f^eq - f) + ..., R = M^-1 S M, which is symmetric for
+  // an orthogonal basis, so lambda_{f^eq} = R_f lambda_{f*})
   const C wf = C(p.omega_f), alpha = C(p.alpha);
   C swb = C(0), lwf = C(0), qeq = C(0);
+  C af[9];  // lambda_{f^eq}
+  C dfe[9];  // f^eq - f (MRT)
+  if constexpr (MRT) {
+    C rate[9];
+    mrt_rates_f(p, wf, rate);
+    mrt_relax<C, false>(rate, a, a, af);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) af[i] = wf * a[i];
+  }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     swb += C(w_of(i) * src_bracket(i)) * a[i];
     const C feq = i == 0 ? phi - C(1.0 - w_of(0)) * alpha * mu : C(w_of(i)) * alpha * mu;
-    lwf += a[i] * (feq - f[i]);
-    qeq += C(i == 0 ? -(1.0 - w_of(0)) : w_of(i)) * (wf * a[i]);
+    if constexpr (MRT)
+      dfe[i] = feq - f[i];
+    else
+      lwf += a[i] * (feq - f[i]);
+    qeq += C(i == 0 ? -(1.0 - w_of(0)) : w_of(i)) * af[i];
   }
-  C lphi = wf * a[0];       // d f^eq_0 / d phi = 1
+  if constexpr (MRT) {
+    // w_f is the rate of the phi and j moments: d/dw_f = sum over them of
+    // (M a)_k (M (f^eq - f))_k / |row k|^2
+    C ma[9], md[9];
+    mom_fwd(a, ma);
+    mom_fwd(dfe, md);
+    lwf = ma[0] * md[0] * C(1.0 / 9) + (ma[3] * md[3] + ma[5] * md[5]) * C(1.0 / 6);
+  }
+  C lphi = af[0];           // d f^eq_0 / d phi = 1
   const C lmu = alpha * qeq;
   th[0] += (double)(mu * qeq);          // d/d alpha
   th[1] += (double)(-(wf * wf) * lwf);  // d/d tau_f through 1/tau_f
@@ -282,8 +305,20 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   const C lSp_out = -half * swb;
 
   // ---- hydrodynamic collision: g* = g - w_g (g - g^eq) + k_G G~
+  // (MRT: g* = g + R_g (g^eq - g) + (I - R_g/2) G~, so lambda_{g^eq} = R_g c
+  // and lambda_{G~} = c - R_g c / 2)
   C lwg = C(0), lkG = C(0), lp = C(0), lrho = C(0);
   C lux = C(0), luy = C(0), lFx = C(0), lFy = C(0), lgrx = C(0), lgry = C(0);
+  C cg[9];           // lambda_{g^eq}
+  C dge[9], Gtv[9];  // g^eq - g and G~ (MRT)
+  if constexpr (MRT) {
+    C rate[9];
+    mrt_rates_g(p, wg, rate);
+    mrt_relax<C, false>(rate, c, c, cg);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) cg[i] = wg * c[i];
+  }
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const C cxi = C(cx_of(i)), cyi = C(cy_of(i)), wi = C(w_of(i));
@@ -293,16 +328,21 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
     const C si = wi * (three * cu + C(4.5) * cu * cu - C(1.5) * uu);
     const C pw = C(INV_CS2 * (w_of(i) - (i == 0 ? 1.0 : 0.0)));
     const C geq = pr * pw + rho * si;
-    lwg += c[i] * (geq - g[i]);
     const C Gt = three * wi * (cF + cu * cr);
-    lkG += c[i] * Gt;
-    const C lgeq = wg * c[i];
+    if constexpr (MRT) {
+      dge[i] = geq - g[i];
+      Gtv[i] = Gt;
+    } else {
+      lwg += c[i] * (geq - g[i]);
+      lkG += c[i] * Gt;
+    }
+    const C lgeq = cg[i];
     lp += lgeq * pw;
     lrho += lgeq * si;
     const C rl = rho * lgeq * wi;
     lux += rl * (three * cxi + C(9.0) * cu * cxi - three * ux);
     luy += rl * (three * cyi + C(9.0) * cu * cyi - three * uy);
-    const C kc = kG * c[i] * three * wi;
+    const C kc = (MRT ? c[i] - half * cg[i] : kG * c[i]) * three * wi;
     lFx += kc * cxi;
     lFy += kc * cyi;
     lux += kc * cr * cxi;
@@ -310,7 +350,16 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
     lgrx += kc * cu * cxi;
     lgry += kc * cu * cyi;
   }
-  // tau_g = 1/2 + 3 nu(phi); w_g = 1/tau_g; k_G = 1 - w_g/2
+  // tau_g = 1/2 + 3 nu(phi); w_g = 1/tau_g; k_G = 1 - w_g/2 (MRT: w_g is the
+  // rate of j, p_xx and p_xy, in S and in I - S/2)
+  if constexpr (MRT) {
+    C mc[9], md[9], mG[9];
+    mom_fwd(c, mc);
+    mom_fwd(dge, md);
+    mom_fwd(Gtv, mG);
+    lwg = (mc[3] * md[3] + mc[5] * md[5]) * C(1.0 / 6) + (mc[7] * md[7] + mc[8] * md[8]) * C(0.25);
+    lkG = (mc[3] * mG[3] + mc[5] * mG[5]) * C(1.0 / 6) + (mc[7] * mG[7] + mc[8] * mG[8]) * C(0.25);
+  }
   const C lwg_t = lwg - half * lkG;
   const C lnu = three * (-(wg * wg) * lwg_t);
   C dnu_phi, dnu_A, dnu_B;
@@ -345,7 +394,8 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   // ---- outputs
 #pragma unroll
   for (int i = 0; i < 9; ++i)
-    o.lg[i] = (one - wg) * c[i] + C(cx_of(i)) * lmx + C(cy_of(i)) * lmy + (i ? lsnz : C(0));
+    o.lg[i] = (MRT ? c[i] - cg[i] : (one - wg) * c[i]) + C(cx_of(i)) * lmx + C(cy_of(i)) * lmy +
+              (i ? lsnz : C(0));
   o.lS = INIT ? C(0) : lSp_out;
   o.lphi = lphi;
   o.lmu = lmu;
@@ -355,7 +405,7 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   o.lgmy = lgmy;
 }
 
-template <typename T, bool INIT>
+template <typename T, bool INIT, bool MRT = false>
 __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict__ B,
                                                  const T* __restrict__ dphi,
                                                  const T* __restrict__ mupl,
@@ -370,7 +420,7 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
     const long long n = (long long)p.nx * p.ny;
     const unsigned kd = (unsigned)(y * p.nx + x);
     KaCell<T> o;
-    ka_cell<T, INIT>(p, B, dphi, mupl, lam_in, x, y, o, th);
+    ka_cell<T, INIT, MRT>(p, B, dphi, mupl, lam_in, x, y, o, th);
 #pragma unroll
     for (int i = 0; i < 9; ++i) uni(lam_out + (9 + i) * n)[kd] = o.lg[i];
     uni(lam_out + 18 * n)[kd] = o.lS;
@@ -414,7 +464,7 @@ __device__ __forceinline__ int pre_off(int v, int c, int n, int wall, int (&out)
 // tile, is 16 % of the tile's cells.
 constexpr int KM_TX = 64, KM_TY = 16, KM_THREADS = 256;
 
-template <typename T, bool INIT>
+template <typename T, bool INIT, bool MRT = false>
 __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __restrict__ dphi,
                                                   const T* __restrict__ lam_in, T* __restrict__ lam_out,
                                                   AdjWork<T> w, double* __restrict__ th_part, int ntx) {
@@ -544,8 +594,16 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
         gt += C(INV_CS2 * w_of(d)) * t;
       }
       const C lphi = in.lphi + gt + C(p.beta4 * 0.25) * d2psi_b<C>(p, ph) * lmt - C(p.kappa) * lt;
+      if constexpr (MRT) {
+        C rate[9], ra[9];  // lambda_f = (I - R_f) lambda_{f*} + lambda_phi
+        mrt_rates_f(p, C(p.omega_f), rate);
+        mrt_relax<C, false>(rate, in.a, in.a, ra);
 #pragma unroll
-      for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = k1 * in.a[j] + lphi;
+        for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = (in.a[j] - ra[j]) + lphi;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = k1 * in.a[j] + lphi;
+      }
     };
     constexpr int NR = KM_TY / (KM_THREADS / KM_TX);  // rows per thread
     const int ty0 = threadIdx.x / KM_TX;
@@ -592,6 +650,7 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
       th[1] += (double)(dpsi_b<C>(p, ph) * lmt);
       const C lphi = w.lphi[kd] + grad_T<C>(p, w.lgpx, w.lgpy, x, y) +
                      C(p.beta4 * 0.25) * d2psi_b<C>(p, ph) * lmt - C(p.kappa) * lt;
+      C av[9];
 #pragma unroll
       for (int j = 0; j < 9; ++j) {
         C a = C(0);
@@ -604,7 +663,17 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
           const auto la = wall ? uni(lam_in + opp_of(j) * n) : uni(lam_in + j * n);
           a = la[k];
         }
-        uni(lam_out + j * n)[kd] = k1 * a + lphi;
+        av[j] = a;
+      }
+      if constexpr (MRT) {
+        C rate[9], ra[9];  // lambda_f = (I - R_f) lambda_{f*} + lambda_phi
+        mrt_rates_f(p, C(p.omega_f), rate);
+        mrt_relax<C, false>(rate, av, av, ra);
+#pragma unroll
+        for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = (av[j] - ra[j]) + lphi;
+      } else {
+#pragma unroll
+        for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = k1 * av[j] + lphi;
       }
     }
   }

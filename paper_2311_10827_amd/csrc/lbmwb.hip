@@ -425,11 +425,19 @@ int adjoint_step_impl(lbm_ctx* c, T* state, const T* lam_in, T* lam_out, bool ha
   }
   const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
   const AdjWork<T> w = adj_work<T>(c);
-  hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu, lam_in,
-                     lam_out, w, c->th_part, c->ntx2);
-  LAUNCHCHK(c);
-  hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(c->ntxm * c->ntym), dim3(KM_THREADS), 0, c->stream, c->kp,
-                     dphi, lam_in, lam_out, w, c->th_part, c->ntxm);
+  if (c->kp.collision == LBM_MRT) {
+    hipLaunchKernelGGL((ka_local<T, false, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu,
+                       lam_in, lam_out, w, c->th_part, c->ntx2);
+    LAUNCHCHK(c);
+    hipLaunchKernelGGL((ka_mu_phi<T, false, true>), dim3(c->ntxm * c->ntym), dim3(KM_THREADS), 0, c->stream,
+                       c->kp, dphi, lam_in, lam_out, w, c->th_part, c->ntxm);
+  } else {
+    hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu,
+                       lam_in, lam_out, w, c->th_part, c->ntx2);
+    LAUNCHCHK(c);
+    hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(c->ntxm * c->ntym), dim3(KM_THREADS), 0, c->stream,
+                       c->kp, dphi, lam_in, lam_out, w, c->th_part, c->ntxm);
+  }
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -703,10 +711,6 @@ size_t lbm_adjoint_workspace_bytes(const lbm_params* p) {
 
 int lbm_adjoint_attach(lbm_ctx* c, void* adj_workspace) {
   if (!c || !adj_workspace || ((uintptr_t)adj_workspace & 255)) return LBM_EINVAL;
-  if (c->kp.collision != LBM_BGK) {
-    c->err = "lbm_adjoint_attach: the adjoint covers the BGK collision only";
-    return LBM_EINVAL;
-  }
   c->adj = static_cast<char*>(adj_workspace);
   c->th_part = reinterpret_cast<double*>(c->adj + ADJ_PLANES * adj_plane_bytes(&c->p));
   const long long tiles = (long long)c->ntx2 * c->nty2;

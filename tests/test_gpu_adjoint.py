@@ -310,3 +310,78 @@ def test_dot_product_viscosity_forms(form):
         lhs = _dot(lam1, _lam_pack(Jf, Jg, JS))
         say(f"  {THETA[q]}: lhs {lhs:.16e} rhs {g6[q] * scale:.16e}")
         assert abs(lhs - g6[q] * scale) <= 1e-11 * max(abs(lhs), 1e-300), (THETA[q], lhs, g6[q] * scale)
+
+
+@pytest.mark.parametrize("bc", [(0, 0), (1, 0), (1, 1)])
+def test_dot_product_mrt(bc):
+    # one step's transpose under the MRT collision (rates away from BGK's),
+    # with unequal viscosities so that tau_g varies across the interface;
+    # periodic and walled grids take different paths in the stencil pass
+    nx, ny = 23, 17
+    wl = inputs.Workload("adj_mrt", nx, ny, bc_x=bc[0], bc_y=bc[1], rho_A=10.0, rho_B=1.0, nu_A=0.03,
+                         nu_B=0.2, sigma=5e-3, W=4.0, M=0.05, alpha=0.8, nu_form=2, collision=1,
+                         mrt_f=(1.3, 1.1, 1.6, 1.4), mrt_g=(1.5, 1.7))
+    prm = oracle.params_for(wl, gx=3e-6)
+    phi0 = inputs.two_drops(nx, ny, 4.0, 4.0, noise=1e-3, workload_id=22)
+    f, g, Sp = oracle.Sim(prm).init(phi0).step(3).get_state()
+    gp = make_params(wl, precision=64, kappa=prm.kappa, beta=prm.beta, gx=3e-6)
+    say(f"[gpu] adjoint dot product, MRT, bc={bc}")
+    sim = Sim(gp, phi0)
+    sim.set_state(f, g, Sp)
+    sim.enable_adjoint()
+    snap = sim.snapshot()
+    rng = np.random.default_rng(31 + bc[0] + 2 * bc[1])
+    lam1 = rng.standard_normal((19, ny, nx))
+    lout = sim.new_adjoint()
+    sim.adjoint_step(snap, torch.from_numpy(lam1).cuda(), lout)
+    g6 = np.array(sim.adjoint_theta(reset=True))
+    lam0 = lout.cpu().numpy()
+    df = rng.standard_normal(f.shape) * 1e-3
+    dg = rng.standard_normal(g.shape) * 1e-5
+    dS = rng.standard_normal(Sp.shape) * 1e-6
+    _, Jf, _, Jg, _, JS = oracle.TLM(prm).set_state(f, df, g, dg, Sp, dS).step(1).get_state()
+    lhs, rhs = _dot(lam1, _lam_pack(Jf, Jg, JS)), _dot(lam0, _lam_pack(df, dg, dS))
+    say(f"  state: lhs {lhs:.16e} rhs {rhs:.16e}")
+    assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300), (lhs, rhs)
+    scales = np.array([1e-3, 1e-4, 0.1, 0.05, 0.01, 0.01])
+    for q in range(6):
+        dth = np.zeros(6)
+        dth[q] = scales[q]
+        _, Jf, _, Jg, _, JS = oracle.TLM(prm, dth).set_state(f, None, g, None, Sp, None).step(1).get_state()
+        lhs = _dot(lam1, _lam_pack(Jf, Jg, JS))
+        say(f"  {THETA[q]}: lhs {lhs:.16e} rhs {g6[q] * scales[q]:.16e}")
+        assert abs(lhs - g6[q] * scales[q]) <= 1e-11 * max(abs(lhs), 1e-300), (THETA[q], lhs, g6[q] * scales[q])
+
+
+def test_mrt_rollout_gradient_matches_finite_differences():
+    # the checkpointed rollout under MRT, against central differences of the
+    # GPU forward map (64 x 64 FP64, 200 steps)
+    base, theta, th_t, phi0 = _fd_setup()
+    base.collision = 1
+    for k, r in enumerate((1.3, 1.1, 1.6, 1.4)):
+        base.mrt_f[k] = r
+    for k, r in enumerate((1.5, 1.7)):
+        base.mrt_g[k] = r
+    nsteps, K = 200, 50
+    say("[gpu] MRT rollout gradient vs central differences, 64x64 FP64, 200 steps")
+    tgt = Sim(params_from_theta(base, th_t), phi0).step(nsteps).moments(diag=False)["phi"]
+    ph = torch.from_numpy(phi0).cuda().requires_grad_(True)
+    th = torch.tensor(theta, requires_grad=True)
+    L = misfit(rollout(ph, th, base, nsteps, K), tgt)
+    L.backward()
+    gth = th.grad.numpy()
+    gph = ph.grad.cpu().numpy()
+    for k in range(6):
+        h = 1e-6 * abs(theta[k])
+        tp, tm = theta.copy(), theta.copy()
+        tp[k] += h
+        tm[k] -= h
+        fd = (_loss(base, tp, phi0, tgt, nsteps) - _loss(base, tm, phi0, tgt, nsteps)) / (2 * h)
+        say(f"  d/d{['kappa', 'beta', 'M', 'tau_f', 'tau_gA', 'tau_gB'][k]}: adjoint {gth[k]:.10e} fd {fd:.10e}")
+        assert abs(gth[k] - fd) <= 1e-4 * abs(fd) + 1e-12 * abs(float(L))
+    v = np.random.default_rng(10).standard_normal(phi0.shape)
+    h = 1e-6
+    fd = (_loss(base, theta, phi0 + h * v, tgt, nsteps) - _loss(base, theta, phi0 - h * v, tgt, nsteps)) / (2 * h)
+    ad = float(np.sum(gph * v))
+    say(f"  d/dphi0 . v: adjoint {ad:.10e} fd {fd:.10e}")
+    assert abs(ad - fd) <= 1e-4 * abs(fd)
