@@ -66,15 +66,20 @@ def measured_traffic(key: str):
     return rec.get("bytes_per_launch", rec.get("bytes_per_step"))
 
 
-def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl, kernel_path: int = 2):
+# MRT rates of the MRT leg: f (e, eps, q, p), g ((rho, e, eps), q)
+MRT_LEG = dict(collision=1, mrt_f=(1.3, 1.1, 1.6, 1.4), mrt_g=(1.5, 1.7))
+
+
+def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl, kernel_path: int = 2,
+            mrt: bool = False):
     import torch
     from paper_2311_10827_amd.sim import Sim, make_params
 
-    p = make_params(wl, precision=prec, kernel_path=kernel_path)
+    p = make_params(wl, precision=prec, kernel_path=kernel_path, **(MRT_LEG if mrt else {}))
     sim = Sim(p, phi0_dev, device=phi0_dev.device)
     stream = sim.stream
     ncell = wl.nx * wl.ny
-    tag = f"fp{prec}{'' if kernel_path == 2 else ' two-kernel'}"
+    tag = f"fp{prec}{'' if kernel_path == 2 else ' two-kernel'}{' MRT' if mrt else ''}"
     log(f"[bench] {tag}: warmup {warmup}")
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -102,7 +107,7 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
     avg = kms / n
     alg = STEP_BYTES[prec] if kernel_path == 2 else TWO_KERNEL_BYTES[prec]
     ach = alg * ncell / (avg * 1e-3) / 1e9
-    traffic = measured_traffic(str(prec) if kernel_path == 2 else f"two_kernel_{prec}")
+    traffic = None if mrt else measured_traffic(str(prec) if kernel_path == 2 else f"two_kernel_{prec}")
     return {
         "mlups": ncell * steps / (ms * 1e-3) / 1e6,
         "ms_per_step": ms / steps,
@@ -251,6 +256,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-two-kernel", action="store_true")
+    ap.add_argument("--no-mrt", action="store_true")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-K", type=int, default=100)
     ap.add_argument("--adjoint-only", action="store_true",
@@ -282,6 +288,9 @@ def main():
     r2k = None
     if not args.no_two_kernel:
         r2k = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, kernel_path=1)
+    rmrt = None
+    if not args.no_mrt:
+        rmrt = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, mrt=True)
     del phi0_dev
     torch.cuda.empty_cache()
     copy_gbps = None if args.no_copy else stream_copy_probe(dev)
@@ -322,6 +331,11 @@ def main():
             "value": round(r2k["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r2k["ms_per_step"], 4),
             "algorithmic_bytes_per_cell": TWO_KERNEL_BYTES[32], "roofline": r2k["roofline"],
             "measured_bytes_frac": r2k["measured_bytes_frac"],
+        },
+        "mrt_fp32": None if rmrt is None else {
+            "value": round(rmrt["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(rmrt["ms_per_step"], 4),
+            "kernel_ms": round(rmrt["kernel_ms"], 4), "algorithmic_bytes_per_cell": STEP_BYTES[32],
+            "roofline": rmrt["roofline"], "rates": {"f": MRT_LEG["mrt_f"], "g": MRT_LEG["mrt_g"]},
         },
         "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
