@@ -319,36 +319,74 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
 #pragma unroll
     for (int i = 0; i < 9; ++i) cg[i] = wg * c[i];
   }
+  if constexpr (!MRT) {
+    // BGK: lambda_{g^eq} = w_g c and lambda_{G~} = k_G c, so every sum over
+    // the links below is a combination of the weighted lattice moments
+    // sum_i w_i c_i {1, c_x, c_y, c_x^2, c_x c_y, c_y^2} of the seed c.
+    const C ax = (c[1] + c[3]), ay = (c[2] + c[4]), dsum = (c[5] + c[6]) + (c[7] + c[8]);
+    const C w1 = C(1.0 / 9), w5 = C(1.0 / 36);
+    const C m0 = C(4.0 / 9) * c[0] + w1 * (ax + ay) + w5 * dsum;
+    const C mx = w1 * (c[1] - c[3]) + w5 * ((c[5] - c[6]) + (c[8] - c[7]));
+    const C my = w1 * (c[2] - c[4]) + w5 * ((c[5] + c[6]) - (c[7] + c[8]));
+    const C mxx = w1 * ax + w5 * dsum, myy = w1 * ay + w5 * dsum;
+    const C mxy = w5 * ((c[5] + c[7]) - (c[6] + c[8]));
+    // sum_i c_i s_i(u) (eq. Siu) and sum_i c_i g_i
+    const C cs = three * (ux * mx + uy * my) +
+                 C(4.5) * (ux * ux * mxx + C(2) * ux * uy * mxy + uy * uy * myy) - C(1.5) * uu * m0;
+    C cgsum = c[0] * g[0];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const C cxi = C(cx_of(i)), cyi = C(cy_of(i)), wi = C(w_of(i));
-    const C cu = cxi * ux + cyi * uy;
-    const C cF = cxi * Fx + cyi * Fy;
-    const C cr = cxi * grx + cyi * gry;
-    const C si = wi * (three * cu + C(4.5) * cu * cu - C(1.5) * uu);
-    const C pw = C(INV_CS2 * (w_of(i) - (i == 0 ? 1.0 : 0.0)));
-    const C geq = pr * pw + rho * si;
-    const C Gt = three * wi * (cF + cu * cr);
-    if constexpr (MRT) {
-      dge[i] = geq - g[i];
-      Gtv[i] = Gt;
-    } else {
-      lwg += c[i] * (geq - g[i]);
-      lkG += c[i] * Gt;
+    for (int i = 1; i < 9; ++i) cgsum += c[i] * g[i];
+    // d/dw_g: sum_i c_i (g^eq_i - g_i), g^eq_i = p pw_i + rho s_i, pw_i = 3 (w_i - [i = 0])
+    lwg = pr * three * (m0 - c[0]) + rho * cs - cgsum;
+    // d/dk_G: sum_i c_i G~_i, G~_i = 3 w_i (c_i.F + (c_i.u)(c_i.grad rho))
+    lkG = three * (Fx * mx + Fy * my +
+                   (ux * grx * mxx + (ux * gry + uy * grx) * mxy + uy * gry * myy));
+    // through g^eq (lambda_{g^eq} = w_g c)
+    lp = wg * three * (m0 - c[0]);
+    lrho = wg * cs;
+    const C rw = rho * wg;
+    lux = rw * (three * mx + C(9) * (ux * mxx + uy * mxy) - three * ux * m0);
+    luy = rw * (three * my + C(9) * (ux * mxy + uy * myy) - three * uy * m0);
+    // through G~ (lambda_{G~} = k_G c)
+    const C k3 = three * kG;
+    lFx = k3 * mx;
+    lFy = k3 * my;
+    lux += k3 * (grx * mxx + gry * mxy);
+    luy += k3 * (grx * mxy + gry * myy);
+    lgrx = k3 * (ux * mxx + uy * mxy);
+    lgry = k3 * (ux * mxy + uy * myy);
+  } else {
+  #pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const C cxi = C(cx_of(i)), cyi = C(cy_of(i)), wi = C(w_of(i));
+      const C cu = cxi * ux + cyi * uy;
+      const C cF = cxi * Fx + cyi * Fy;
+      const C cr = cxi * grx + cyi * gry;
+      const C si = wi * (three * cu + C(4.5) * cu * cu - C(1.5) * uu);
+      const C pw = C(INV_CS2 * (w_of(i) - (i == 0 ? 1.0 : 0.0)));
+      const C geq = pr * pw + rho * si;
+      const C Gt = three * wi * (cF + cu * cr);
+      if constexpr (MRT) {
+        dge[i] = geq - g[i];
+        Gtv[i] = Gt;
+      } else {
+        lwg += c[i] * (geq - g[i]);
+        lkG += c[i] * Gt;
+      }
+      const C lgeq = cg[i];
+      lp += lgeq * pw;
+      lrho += lgeq * si;
+      const C rl = rho * lgeq * wi;
+      lux += rl * (three * cxi + C(9.0) * cu * cxi - three * ux);
+      luy += rl * (three * cyi + C(9.0) * cu * cyi - three * uy);
+      const C kc = (MRT ? c[i] - half * cg[i] : kG * c[i]) * three * wi;
+      lFx += kc * cxi;
+      lFy += kc * cyi;
+      lux += kc * cr * cxi;
+      luy += kc * cr * cyi;
+      lgrx += kc * cu * cxi;
+      lgry += kc * cu * cyi;
     }
-    const C lgeq = cg[i];
-    lp += lgeq * pw;
-    lrho += lgeq * si;
-    const C rl = rho * lgeq * wi;
-    lux += rl * (three * cxi + C(9.0) * cu * cxi - three * ux);
-    luy += rl * (three * cyi + C(9.0) * cu * cyi - three * uy);
-    const C kc = (MRT ? c[i] - half * cg[i] : kG * c[i]) * three * wi;
-    lFx += kc * cxi;
-    lFy += kc * cyi;
-    lux += kc * cr * cxi;
-    luy += kc * cr * cyi;
-    lgrx += kc * cu * cxi;
-    lgry += kc * cu * cyi;
   }
   // tau_g = 1/2 + 3 nu(phi); w_g = 1/tau_g; k_G = 1 - w_g/2 (MRT: w_g is the
   // rate of j, p_xx and p_xy, in S and in I - S/2)
