@@ -60,3 +60,39 @@ def test_random_configuration(k, path):
     assert d32["n_nonfinite"] == 0
     assert np.abs(m32["phi"] - om["phi"]).max() <= 1e-5
     assert max(np.abs(m32["ux"] - om["ux"]).max(), np.abs(m32["uy"] - om["uy"]).max()) <= 1e-6
+
+
+N_VARIANT_CASES = 8
+
+
+def _variant_config(k):
+    # the random configurations above, with a viscosity form and a collision
+    # operator drawn too (MRT rates uniform in (0.6, 1.9))
+    wl, phi0, over = _config(k)
+    rng = np.random.default_rng(231110827 + 3000 + k)
+    wl.nu_form = int(rng.integers(3))
+    wl.collision = int(rng.integers(2))
+    wl.mrt_f = tuple(float(v) for v in rng.uniform(0.6, 1.9, size=4))
+    wl.mrt_g = tuple(float(v) for v in rng.uniform(0.6, 1.9, size=2))
+    return wl, phi0, over
+
+
+@pytest.mark.parametrize("path", [1, 2])
+@pytest.mark.parametrize("k", range(N_VARIANT_CASES))
+def test_random_configuration_viscosity_and_collision(k, path):
+    wl, phi0, over = _variant_config(k)
+    say(f"[gpu] random variant {k}: {wl.nx}x{wl.ny} bc=({wl.bc_x},{wl.bc_y}) nu_form={wl.nu_form} "
+        f"collision={wl.collision} kernel_path={path}")
+    o = oracle_sim(wl, phi0, **over)
+    g64 = gpu_sim(wl, phi0, 64, kernel_path=path, **over)
+    g32 = gpu_sim(wl, phi0, 32, kernel_path=path, **over)
+    for n in (0, 1, 36):
+        o.step(n)
+        g64.step(n)
+        g32.step(n)
+        compare_state(gpu_state(g64), o.get_state(), 1e-12)
+    om = o.moments()
+    m32, d32 = gpu_moments(g32)
+    assert d32["n_nonfinite"] == 0
+    assert np.abs(m32["phi"] - om["phi"]).max() <= 1e-5
+    assert max(np.abs(m32["ux"] - om["ux"]).max(), np.abs(m32["uy"] - om["uy"]).max()) <= 1e-6
