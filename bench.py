@@ -174,17 +174,23 @@ def cpu_baseline(wl, seconds: float):
     }
 
 
-def adjoint_leg(nsteps: int, K: int):
+def adjoint_leg(nsteps: int, K: int, n: int = 0):
     """Inverse-problem gradient on the 1024^2 two-drop workload (FP32): the
     adjoint step's cost, including its share of the checkpoint recompute,
     relative to a forward step on the faster of the two step forms at this
-    size (the forward state fits in the GPU's caches here)."""
+    size (the forward state fits in the GPU's caches here).  n > 0: the same
+    workload on an n x n grid, drop radius scaled with it."""
+    import dataclasses
+
     import torch
     from paper_2311_10827_amd import inputs
     from paper_2311_10827_amd.adjoint import misfit, params_from_theta, rollout
     from paper_2311_10827_amd.sim import Sim, derive, make_params
 
     wl = inputs.ADJOINT
+    if n:
+        wl = dataclasses.replace(wl, name=f"adjoint_{n}", nx=n, ny=n,
+                                 extra={**wl.extra, "R": wl.extra["R"] * n / wl.nx})
     base = make_params(wl, precision=32)
     d = derive(base)
     theta = [d["kappa"], d["beta"], base.M, d["tau_f"], d["tau_gA"], d["tau_gB"]]
@@ -227,7 +233,7 @@ def adjoint_leg(nsteps: int, K: int):
         L.backward()
     t_bwd = stats["backward_s"] * 1e3 / nsteps
     return {
-        "workload": "adjoint_1024: 1024x1024 two drops R 100, density ratio 100, FP32, "
+        "workload": f"{wl.name}: {wl.nx}x{wl.ny} two drops R {wl.extra['R']:g}, density ratio 100, FP32, "
                     f"{nsteps} steps, checkpoint every {K}",
         "forward_ms_per_step": round(t_fwd[kp_best], 5),
         "forward_ms_per_step_fused": round(t_fwd[2], 5),
@@ -272,7 +278,8 @@ def main():
     from paper_2311_10827_amd import inputs
 
     if args.adjoint_only:
-        print(json.dumps({"adjoint": adjoint_leg(args.adjoint_steps, args.adjoint_K)}), flush=True)
+        print(json.dumps({"adjoint": adjoint_leg(args.adjoint_steps, args.adjoint_K),
+                          "adjoint_2048": adjoint_leg(args.adjoint_steps, args.adjoint_K, 2048)}), flush=True)
         return
 
     wl = inputs.THROUGHPUT
@@ -295,6 +302,8 @@ def main():
     torch.cuda.empty_cache()
     copy_gbps = None if args.no_copy else stream_copy_probe(dev)
     adj = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K)
+    # the same at 2048^2, where the forward state no longer fits in the caches
+    adj2 = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K, 2048)
     cpu = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds)
 
     out = {
@@ -340,6 +349,9 @@ def main():
         "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),
         "adjoint_forward_ratio": None if adj is None else adj["ratio"],
         "adjoint": adj,
+        "adjoint_2048": None if adj2 is None else {
+            k: adj2[k] for k in ("workload", "forward_ms_per_step", "forward_reference",
+                                 "adjoint_ms_per_step_incl_recompute", "ratio")},
         "diag_after": r32["diag_after"],
     }
     print(json.dumps(out), flush=True)

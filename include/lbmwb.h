@@ -84,8 +84,8 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
  *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
  *                  diagnostic pass every k steps (see lbm_step).
  *   kernel_path    0: automatic: the fused kernel when the grid gives its
- *                  launch enough workgroups (at least 1024 strips of 256 x
- *                  8 cells in FP32, 512 in FP64), else the two kernels;
+ *                  launch enough workgroups (at least 512 strips of 256 x 8
+ *                  cells), else the two kernels;
  *                  1: the phi/mu pass and the collide-stream pass as two
  *                  kernels; 2: one fused kernel per step (phi and mu kept
  *                  on chip).  All give the same results bit for bit.

@@ -499,7 +499,19 @@ __device__ __forceinline__ int mod_pos(int a, int m) {
   return r < 0 ? r + m : r;
 }
 
-template <typename T, int MODE, bool WRITE_PHIMU, bool MRT = false>
+// A population store: streaming (non-temporal) when NT, else ordinary.
+template <bool NT, typename T>
+__device__ __forceinline__ void pop_store(T v, T* ptr) {
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, ptr);
+  else
+    *ptr = v;
+}
+
+// NT: streaming population stores, for states larger than the last-level
+// cache (nothing reads them before they leave it); ordinary stores when the
+// state fits there, so that the next step finds them in it.
+template <typename T, int MODE, bool WRITE_PHIMU, bool MRT = false, bool NT = true>
 __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T* Bin, T* Bout, const T* Spin,
                                                              T* Spout, T* __restrict__ dphi_out,
                                                              T* __restrict__ mu_out,
@@ -629,15 +641,14 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
       if (active) row_load(y + 1, q, Sp);
     }
     if (active) {
-      // streaming stores: nothing reads them before they leave the caches
       const unsigned o = (unsigned)(y * p.pitch + x);
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        __builtin_nontemporal_store(fo[i], Bout + i * p.ps + o);
-        __builtin_nontemporal_store(go[i], Bout + (9 + i) * p.ps + o);
+        pop_store<NT>(fo[i], Bout + i * p.ps + o);
+        pop_store<NT>(go[i], Bout + (9 + i) * p.ps + o);
       }
-      if constexpr (std::is_same<T, float>::value) __builtin_nontemporal_store(lo, Bout + LO_PLANE * p.ps + o);
-      __builtin_nontemporal_store((T)c.S, Spout + o);
+      if constexpr (std::is_same<T, float>::value) pop_store<NT>(lo, Bout + LO_PLANE * p.ps + o);
+      pop_store<NT>((T)c.S, Spout + o);
       if (DIAG) {
         const bool fin = isfinite(c.phi) && isfinite(c.mu) && isfinite(c.ux) && isfinite(c.uy) &&
                          isfinite(c.p);

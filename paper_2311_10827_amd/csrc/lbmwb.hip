@@ -37,6 +37,7 @@ struct lbm_ctx {
   int64_t step;
   int ntx1, nty1, ntx2, nty2;
   int ntxf, ntyf, hf;   // strips of the fused step kernel and their height
+  bool fused_nt;        // the fused step stores streaming (state above the cache size)
   int ntxm, ntym;       // tiles of ka_mu_phi (no more than the K2 tiles, whose
                         // count sizes the parameter partials)
   bool fused;           // lbm_step runs the fused kernel
@@ -122,7 +123,10 @@ constexpr int ADJ_PLANES = 7;
 constexpr long long FUSED_MIN_BLOCKS = 2048;
 // kernel_path 0 runs the fused step when the grid gives at least this many
 // strips of 256 x 8 cells
-constexpr long long FUSED_AUTO_STRIPS_32 = 1024, FUSED_AUTO_STRIPS_64 = 512;
+constexpr long long FUSED_AUTO_STRIPS_32 = 512, FUSED_AUTO_STRIPS_64 = 512;
+// the fused step stores streaming above this state size (MI355X has a
+// 256 MB last-level cache; a state that fits is read back from it)
+constexpr size_t FUSED_CACHED_STATE_BYTES = (size_t)224 << 20;
 
 size_t adj_plane_bytes(const lbm_params* p) {
   return round_up((size_t)p->nx * p->ny * (p->precision == 32 ? 4 : 8), 256);
@@ -218,15 +222,25 @@ int launch_collide(lbm_ctx* c, MomOut mo) {
                                  S_plane<T>(c));
 }
 
+template <typename T, int MODE, bool WRITE_PHIMU, bool MRT, bool NT>
+void launch_fused_k(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
+  hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU, MRT, NT>), dim3(c->ntxf * c->ntyf), dim3(Strip<T>::W),
+                     0, c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf, c->hf);
+}
 template <typename T, int MODE, bool WRITE_PHIMU>
 int launch_fused(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
-  if (c->kp.collision == LBM_MRT)
-    hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU, true>), dim3(c->ntxf * c->ntyf),
-                       dim3(Strip<T>::W), 0, c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials,
-                       c->ntxf, c->hf);
-  else
-    hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU>), dim3(c->ntxf * c->ntyf), dim3(Strip<T>::W),
-                       0, c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf, c->hf);
+  const bool mrt = c->kp.collision == LBM_MRT;
+  if (c->fused_nt) {
+    if (mrt)
+      launch_fused_k<T, MODE, WRITE_PHIMU, true, true>(c, Bin, Bout, Sin, Sout, dphi, mu);
+    else
+      launch_fused_k<T, MODE, WRITE_PHIMU, false, true>(c, Bin, Bout, Sin, Sout, dphi, mu);
+  } else {
+    if (mrt)
+      launch_fused_k<T, MODE, WRITE_PHIMU, true, false>(c, Bin, Bout, Sin, Sout, dphi, mu);
+    else
+      launch_fused_k<T, MODE, WRITE_PHIMU, false, false>(c, Bin, Bout, Sin, Sout, dphi, mu);
+  }
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -552,11 +566,12 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   {
     // Automatic choice: the fused kernel marches its strips row by row, so
     // on grids that give it few strips even at the lowest height its serial
-    // rows cost more than the second kernel's HBM round trip of phi and mu
-    // (measured crossover: 1024^2 in FP64, 2048^2 in FP32).
+    // rows cost more than the second kernel's round trip of phi and mu
+    // (measured crossover: between 768^2 and 1024^2 in both precisions).
     const long long strips8 = (long long)c->ntxf * ((p->ny + 7) / 8);
     const long long need = p->precision == 32 ? FUSED_AUTO_STRIPS_32 : FUSED_AUTO_STRIPS_64;
     c->fused = p->kernel_path == 2 || (p->kernel_path == 0 && strips8 >= need);
+    c->fused_nt = L.state_bytes > FUSED_CACHED_STATE_BYTES;
   }
   c->partials = reinterpret_cast<double*>(c->ws);
   c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
