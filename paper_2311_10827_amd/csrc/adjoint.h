@@ -198,9 +198,10 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   const long long n = (long long)p.nx * p.ny;  // plane stride of the dense planes
   const unsigned kd = (unsigned)(y * p.nx + x);  // n <= INT32_MAX
   const C half = C(0.5), one = C(1.0), three = C(3.0);
-  // ---- forward recompute at this cell
+  // ---- forward recompute at this cell (FP32 does not read f_0: see below)
+  constexpr bool F0 = !std::is_same<T, float>::value;
   Pops<T> q;
-  gather<true>(B, p, x, y, q);
+  gather<true, T, true, F0>(B, p, x, y, q);
   Nbhd<T> nb;
   load_nbhd(p, dphi, mupl, x, y, nb);
   const C phi_ref = C(p.phi_ref);
@@ -210,11 +211,15 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
 #pragma unroll
     for (int b = 0; b < 3; ++b) ph3[a][b] = nb.ph[a][b] + phi_ref;
   const auto& mu3 = nb.mu;
+  // phi = sum_i f_i, so f^eq_0 - f_0 = sum_{i!=0} f_i - (1 - w_0) alpha mu,
+  // which the FP32 forward step uses too: FP32 skips the two planes of f_0.
+  // FP64 takes f_0 itself, keeping the tau_f partial, a small sum of large
+  // terms, at FP64 rounding of its own operands.
   C f[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) f[i] = q.f[i];
-  if constexpr (std::is_same<T, float>::value) f[0] += q.lo;
-  f[0] += phi_ref;
+  for (int i = 1; i < 9; ++i) f[i] = q.f[i];
+  f[0] = F0 ? C(q.f[0]) + phi_ref : C(0);
+  const C s8 = ((f[1] + f[2]) + (f[3] + f[4])) + ((f[5] + f[6]) + (f[7] + f[8]));
   const C* g = q.g;
   const C phi = ph3[1][1], mu = mu3[1][1];
   const C k3 = C(1.0 / 3.0), k12 = C(1.0 / 12.0);
@@ -282,11 +287,13 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     swb += C(w_of(i) * src_bracket(i)) * a[i];
-    const C feq = i == 0 ? phi - C(1.0 - w_of(0)) * alpha * mu : C(w_of(i)) * alpha * mu;
+    const C dfi = i != 0 ? C(w_of(i)) * alpha * mu - f[i]
+                  : F0   ? (phi - C(1.0 - w_of(0)) * alpha * mu) - f[0]
+                         : s8 - C(1.0 - w_of(0)) * alpha * mu;
     if constexpr (MRT)
-      dfe[i] = feq - f[i];
+      dfe[i] = dfi;
     else
-      lwf += a[i] * (feq - f[i]);
+      lwf += a[i] * dfi;
     qeq += C(i == 0 ? -(1.0 - w_of(0)) : w_of(i)) * af[i];
   }
   if constexpr (MRT) {

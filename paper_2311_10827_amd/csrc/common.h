@@ -246,11 +246,12 @@ struct Pops {
   T lo;  // FP32 only: low word of f_0
 };
 
-// WITH_G: also gather g.  WITH_F: gather f (and the low word of f_0).
+// WITH_G: also gather g.  WITH_F: gather f (and the low word of f_0);
+// WITH_F0 = false leaves out f_0 and its low word.
 // Offsets within a plane fit in 32 bits (pitch * ny <= INT32_MAX); the
 // plane of each load is one of two wave-uniform bases (the direction's own
 // or, for a bounce-back lane, the opposite one).
-template <bool WITH_G, typename T, bool WITH_F = true>
+template <bool WITH_G, typename T, bool WITH_F = true, bool WITH_F0 = true>
 __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int x, int y, Pops<T>& q) {
   const PullCols px = pull_cols(x, p.nx, p.bcx);
   const PullCols py = pull_cols(y, p.ny, p.bcy);
@@ -262,7 +263,7 @@ __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int
     const int sy = cy == 1 ? py.m : (cy == -1 ? py.p : y);
     const bool bb = sx < 0 || sy < 0;
     const unsigned off = bb ? own : (unsigned)(sy * p.pitch + sx);
-    if (WITH_F) {
+    if (WITH_F && (WITH_F0 || i != 0)) {
       const T* pf = bb ? B + opp_of(i) * p.ps : B + i * p.ps;
       q.f[i] = pf[off];
     }
@@ -271,7 +272,7 @@ __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int
       q.g[i] = pg[off];
     }
   }
-  if (WITH_F && std::is_same<T, float>::value) q.lo = (B + LO_PLANE * p.ps)[own];
+  if (WITH_F && WITH_F0 && std::is_same<T, float>::value) q.lo = (B + LO_PLANE * p.ps)[own];
 }
 
 // Store one pre-collision population so that the pull gather returns it:
