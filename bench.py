@@ -71,12 +71,13 @@ MRT_LEG = dict(collision=1, mrt_f=(1.3, 1.1, 1.6, 1.4), mrt_g=(1.5, 1.7))
 
 
 def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl, kernel_path: int = 2,
-            mrt: bool = False):
+            mrt: bool = False, bufs=None):
     import torch
     from paper_2311_10827_amd.sim import Sim, make_params
 
     p = make_params(wl, precision=prec, kernel_path=kernel_path, **(MRT_LEG if mrt else {}))
-    sim = Sim(p, phi0_dev, device=phi0_dev.device)
+    state, ws = bufs if bufs is not None else (None, None)
+    sim = Sim(p, phi0_dev, device=phi0_dev.device, state=state, workspace=ws)
     stream = sim.stream
     ncell = wl.nx * wl.ny
     tag = f"fp{prec}{'' if kernel_path == 2 else ' two-kernel'}{' MRT' if mrt else ''}"
@@ -288,16 +289,28 @@ def main():
     phi0 = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
     phi0_dev = torch.from_numpy(phi0).to(dev)
     del phi0
-    r32 = run_gpu(phi0_dev, 32, args.steps, args.warmup, args.kernel_steps, wl)
+    # the FP32 legs share one state allocation: the step time depends on where
+    # in HBM the state lands (up to 10 %), and this keeps the legs comparable
+    import ctypes
+
+    from paper_2311_10827_amd import _lib
+    from paper_2311_10827_amd.sim import make_params
+    p32 = make_params(wl, precision=32)
+    bufs32 = (torch.empty(_lib.load().lbm_state_bytes(ctypes.byref(p32)), dtype=torch.uint8, device=dev),
+              torch.empty(_lib.load().lbm_workspace_bytes(ctypes.byref(p32)), dtype=torch.uint8, device=dev))
+    r32 = run_gpu(phi0_dev, 32, args.steps, args.warmup, args.kernel_steps, wl, bufs=bufs32)
     r64 = None
     if not args.no_fp64:
         r64 = run_gpu(phi0_dev, 64, args.fp64_steps or args.steps, args.warmup, args.kernel_steps, wl)
     r2k = None
     if not args.no_two_kernel:
-        r2k = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, kernel_path=1)
+        r2k = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, kernel_path=1,
+                      bufs=bufs32)
     rmrt = None
     if not args.no_mrt:
-        rmrt = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, mrt=True)
+        rmrt = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, mrt=True,
+                       bufs=bufs32)
+    del bufs32
     del phi0_dev
     torch.cuda.empty_cache()
     copy_gbps = None if args.no_copy else stream_copy_probe(dev)

@@ -153,6 +153,57 @@ __device__ __forceinline__ void mrt_rates_g(const KP& p, C wg, C (&r)[9]) {
   r[5] = wg; r[6] = C(p.mg[1]); r[7] = wg; r[8] = wg;
 }
 
+// The forward step takes MRT as the BGK update plus a correction on the
+// moments whose rate differs from the BGK rate w:
+//   M^-1 S M d = w d + M^-1 (S - w) M d,
+// and with the forcing, M^-1 [S M d + (I - S/2) M G]
+//   = w d + (1 - w/2) G + M^-1 (S - w) M (d - G/2).
+// f: S - w is nonzero on e, eps, q_x, q_y, p_xx, p_xy.
+template <typename C>
+__device__ __forceinline__ void mrt_corr_f(const KP& p, C w, const C (&d)[9], C (&out)[9]) {
+  const C a = (d[1] + d[2]) + (d[3] + d[4]), dd = (d[5] + d[6]) + (d[7] + d[8]);
+  const C jxa = d[1] - d[3], jxd = (d[5] - d[6]) + (d[8] - d[7]);
+  const C jya = d[2] - d[4], jyd = (d[5] + d[6]) - (d[7] + d[8]);
+  const C e = (C(-4) * d[0] - a + C(2) * dd) * ((C(p.mf[0]) - w) * C(1.0 / 36));
+  const C ep = (C(4) * d[0] - C(2) * a + dd) * ((C(p.mf[1]) - w) * C(1.0 / 36));
+  const C kq = (C(p.mf[2]) - w) * C(1.0 / 12), kp = (C(p.mf[3]) - w) * C(0.25);
+  const C qx = (C(-2) * jxa + jxd) * kq, qy = (C(-2) * jya + jyd) * kq;
+  const C pxx = ((d[1] + d[3]) - (d[2] + d[4])) * kp, pxy = ((d[5] + d[7]) - (d[6] + d[8])) * kp;
+  out[0] = C(4) * (ep - e);
+  const C ax = -e - C(2) * ep, dg = C(2) * e + ep;
+  out[1] = ax - C(2) * qx + pxx;
+  out[2] = ax - C(2) * qy - pxx;
+  out[3] = ax + C(2) * qx + pxx;
+  out[4] = ax + C(2) * qy - pxx;
+  out[5] = dg + qx + qy + pxy;
+  out[6] = dg - qx + qy - pxy;
+  out[7] = dg - qx - qy + pxy;
+  out[8] = dg + qx - qy - pxy;
+}
+// g: S - w is nonzero on rho, e, eps (rate mg[0]) and q_x, q_y (mg[1]); z is
+// d - G/2.
+template <typename C>
+__device__ __forceinline__ void mrt_corr_g(const KP& p, C w, const C (&z)[9], C (&out)[9]) {
+  const C a = (z[1] + z[2]) + (z[3] + z[4]), dd = (z[5] + z[6]) + (z[7] + z[8]);
+  const C jxa = z[1] - z[3], jxd = (z[5] - z[6]) + (z[8] - z[7]);
+  const C jya = z[2] - z[4], jyd = (z[5] + z[6]) - (z[7] + z[8]);
+  const C kpr = C(p.mg[0]) - w, kq = (C(p.mg[1]) - w) * C(1.0 / 12);
+  const C r = (z[0] + a + dd) * (kpr * C(1.0 / 9));
+  const C e = (C(-4) * z[0] - a + C(2) * dd) * (kpr * C(1.0 / 36));
+  const C ep = (C(4) * z[0] - C(2) * a + dd) * (kpr * C(1.0 / 36));
+  const C qx = (C(-2) * jxa + jxd) * kq, qy = (C(-2) * jya + jyd) * kq;
+  out[0] = r - C(4) * e + C(4) * ep;
+  const C ax = r - e - C(2) * ep, dg = r + C(2) * e + ep;
+  out[1] = ax - C(2) * qx;
+  out[2] = ax - C(2) * qy;
+  out[3] = ax + C(2) * qx;
+  out[4] = ax + C(2) * qy;
+  out[5] = dg + qx + qy;
+  out[6] = dg - qx + qy;
+  out[7] = dg - qx - qy;
+  out[8] = dg + qx - qy;
+}
+
 // Viscosity across the interface (Sec. 2.3.2).  The paper adopts nu linear in
 // phi (eq. vis); it names the inverse-linear and the exponential forms as the
 // alternatives, read here as 1/nu, respectively ln nu, linear in the phase-A

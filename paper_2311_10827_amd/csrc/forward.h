@@ -228,34 +228,27 @@ __device__ __forceinline__ void cell_f64(const KP& p, const Pops<double>& q, con
   if (!WRITE) return;
   // order-parameter population (Sec. 2.3.1, eqs. BGK, H_i, F_i)
   const double* f = q.f;
-  if constexpr (MRT) {
-    double d[9], rel[9], rate[9];
+  double dfe[9];  // MRT: f^eq - f
 #pragma unroll
-    for (int i = 0; i < 9; ++i)
-      d[i] = (i == 0 ? phi - ((1.0 - w_of(0)) * p.alpha) * mu : (w_of(i) * p.alpha) * mu) - f[i];
-    mrt_rates_f(p, p.omega_f, rate);
-    mrt_relax<double, false>(rate, d, d, rel);
+  for (int i = 0; i < 9; ++i) {
+    const double feq = i == 0 ? phi - ((1.0 - w_of(0)) * p.alpha) * mu : (w_of(i) * p.alpha) * mu;
+    const double Fn = (w_of(i) * S) * src_bracket(i);
+    const double Fo = (w_of(i) * Sp) * src_bracket(i);
+    fo[i] = ((f[i] - p.omega_f * (f[i] - feq)) + Fn) + 0.5 * (Fn - Fo);
+    if constexpr (MRT) dfe[i] = feq - f[i];
+  }
+  if constexpr (MRT) {  // the BGK update above plus the MRT correction
+    double corr[9];
+    mrt_corr_f(p, p.omega_f, dfe, corr);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const double Fn = (w_of(i) * S) * src_bracket(i);
-      const double Fo = (w_of(i) * Sp) * src_bracket(i);
-      fo[i] = ((f[i] + rel[i]) + Fn) + 0.5 * (Fn - Fo);
-    }
-  } else {
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      const double feq = i == 0 ? phi - ((1.0 - w_of(0)) * p.alpha) * mu : (w_of(i) * p.alpha) * mu;
-      const double Fn = (w_of(i) * S) * src_bracket(i);
-      const double Fo = (w_of(i) * Sp) * src_bracket(i);
-      fo[i] = ((f[i] - p.omega_f * (f[i] - feq)) + Fn) + 0.5 * (Fn - Fo);
-    }
+    for (int i = 0; i < 9; ++i) fo[i] += corr[i];
   }
   // hydrodynamic population (Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi)
   const double tau = 0.5 + nu * INV_CS2;
   const double wg = 1.0 / tau;
-  const double kG = MRT ? 1.0 : 1.0 - 1.0 / (2.0 * tau);  // MRT applies (I - S/2) per moment
+  const double kG = 1.0 - 1.0 / (2.0 * tau);
   const double ugr = ux * grx + uy * gry;
-  double dg[9], Gt[9];
+  double z[9];  // MRT: (g^eq - g) - G~/2
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     const double cx = cx_of(i), cy = cy_of(i);
@@ -267,19 +260,14 @@ __device__ __forceinline__ void cell_f64(const KP& p, const Pops<double>& q, con
     const double d = (double)(cy_of(i) * cy_of(i)) - CS2;
     const double dyad = (((ux * grx) * a + (ux * gry) * b) + (uy * grx) * b) + (uy * gry) * d;
     const double Gi = (kG * w_of(i)) * ((ugr + cF * INV_CS2) + dyad * INV_CS2);
-    if constexpr (MRT) {
-      dg[i] = geq - g[i];
-      Gt[i] = Gi;
-    } else {
-      go[i] = (g[i] - wg * (g[i] - geq)) + Gi;
-    }
+    go[i] = (g[i] - wg * (g[i] - geq)) + Gi;
+    if constexpr (MRT) z[i] = (geq - g[i]) - 0.5 * (w_of(i) * ((ugr + cF * INV_CS2) + dyad * INV_CS2));
   }
   if constexpr (MRT) {
-    double rate[9], rel[9];
-    mrt_rates_g(p, wg, rate);
-    mrt_relax<double, true>(rate, dg, Gt, rel);
+    double corr[9];
+    mrt_corr_g(p, wg, z, corr);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) go[i] = g[i] + rel[i];
+    for (int i = 0; i < 9; ++i) go[i] += corr[i];
   }
 }
 
@@ -329,37 +317,33 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
   const float am = (float)p.alpha * mu;
   // f_0 - f_0^eq = -(s8 - (5/9) alpha mu) exactly, since phi = f_0 + s8; add the
   // small increment to hi + lo (FastTwoSum keeps the rounding error in lo).
-  float rel_f[9];  // MRT: M^-1 S M (f^eq - f)
+  float corr_f[9];  // MRT: the correction to the BGK update
   if constexpr (MRT) {
     // f^eq_0 - f_0 = s8 - (5/9) alpha mu exactly (phi = f_0 + s8)
-    float d[9], rate[9];
+    float d[9];
     d[0] = s8 - (float)(5.0 / 9.0) * am;
 #pragma unroll
     for (int i = 1; i < 9; ++i) d[i] = (float)w_of(i) * am - f[i];
-    mrt_rates_f(p, wf, rate);
-    mrt_relax<float, false>(rate, d, d, rel_f);
+    mrt_corr_f(p, wf, d, corr_f);
   }
-  const float inc0 = (MRT ? rel_f[0] : wf * (s8 - (float)(5.0 / 9.0) * am)) +
-                     (float)(w_of(0) * src_bracket(0)) * src;
+  float inc0 = wf * (s8 - (float)(5.0 / 9.0) * am) + (float)(w_of(0) * src_bracket(0)) * src;
+  if constexpr (MRT) inc0 += corr_f[0];
   const float t = q.lo + inc0;
   const float hi = f[0] + t;
   fo[0] = hi;
   fo_lo = t - (hi - f[0]);
 #pragma unroll
-  for (int i = 1; i < 9; ++i)
-    fo[i] = f[i] + (MRT ? rel_f[i] : wf * ((float)w_of(i) * am - f[i])) +
-            (float)(w_of(i) * src_bracket(i)) * src;
+  for (int i = 1; i < 9; ++i) {
+    fo[i] = f[i] + wf * ((float)w_of(i) * am - f[i]) + (float)(w_of(i) * src_bracket(i)) * src;
+    if constexpr (MRT) fo[i] += corr_f[i];
+  }
   const float tau = 0.5f + 3.0f * visc<float>(p, dB);
   const float wg = 1.0f / tau;
-  const float kG = MRT ? 1.0f : 1.0f - 0.5f * wg;  // MRT applies (I - S/2) per moment
+  const float kG = 1.0f - 0.5f * wg;
   const float ge0 = -(float)(5.0 / 3.0) * pr - (float)(2.0 / 3.0) * rho * uu;
-  float dg[9], Gt[9];
-  if constexpr (MRT) {
-    dg[0] = ge0 - g[0];
-    Gt[0] = 0.0f;  // G_0 vanishes: its u.grad(rho) terms cancel
-  } else {
-    go[0] = g[0] + wg * (ge0 - g[0]);
-  }
+  go[0] = g[0] + wg * (ge0 - g[0]);
+  float z[9];  // MRT: (g^eq - g) - G~/2
+  if constexpr (MRT) z[0] = ge0 - g[0];  // G~_0 vanishes: its u.grad(rho) terms cancel
   const float p3 = 3.0f * pr, ruu = 1.5f * rho * uu;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
@@ -369,19 +353,14 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
     const float w = (float)w_of(i);
     const float geq = w * (p3 + rho * (cu * (3.0f + 4.5f * cu)) - ruu);
     const float Gi = kG * 3.0f * w * (cF + cu * cr);
-    if constexpr (MRT) {
-      dg[i] = geq - g[i];
-      Gt[i] = Gi;
-    } else {
-      go[i] = g[i] + wg * (geq - g[i]) + Gi;
-    }
+    go[i] = g[i] + wg * (geq - g[i]) + Gi;
+    if constexpr (MRT) z[i] = (geq - g[i]) - 1.5f * w * (cF + cu * cr);
   }
   if constexpr (MRT) {
-    float rate[9], rel[9];
-    mrt_rates_g(p, wg, rate);
-    mrt_relax<float, true>(rate, dg, Gt, rel);
+    float corr[9];
+    mrt_corr_g(p, wg, z, corr);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) go[i] = g[i] + rel[i];
+    for (int i = 0; i < 9; ++i) go[i] += corr[i];
   }
 }
 

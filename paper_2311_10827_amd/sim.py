@@ -59,6 +59,14 @@ def _dev_f64(a, shape, device) -> Optional[torch.Tensor]:
     return t
 
 
+def _caller_buffer(t: torch.Tensor, nbytes: int, device, what: str) -> torch.Tensor:
+    if t.dtype != torch.uint8 or t.device != torch.device(device) or not t.is_contiguous():
+        raise ValueError(f"{what}: expected a contiguous uint8 tensor on {device}")
+    if t.numel() < nbytes or t.data_ptr() % 256:
+        raise ValueError(f"{what}: needs {nbytes} bytes, 256-byte aligned")
+    return t[:nbytes]
+
+
 def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -70,7 +78,11 @@ def _storage_dtype(precision: int):
 class Sim:
     """One simulation context on one GPU."""
 
-    def __init__(self, params: LbmParams, phi0, ux0=None, uy0=None, device="cuda:0"):
+    def __init__(self, params: LbmParams, phi0, ux0=None, uy0=None, device="cuda:0", state=None,
+                 workspace=None):
+        """``state``/``workspace``: optional uint8 device tensors of at least
+        ``lbm_state_bytes``/``lbm_workspace_bytes`` to use instead of new ones
+        (256-byte aligned; the state is zeroed here)."""
         self.L = _lib.load()
         self.p = params
         self.derived = derive(params)
@@ -83,8 +95,14 @@ class Sim:
         with torch.cuda.device(self.device):
             # zeroed so that the padding between rows and planes (never written
             # by the kernels) is defined and raw snapshots compare bytewise
-            self.state = torch.zeros(nb, dtype=torch.uint8, device=self.device)
-            self.workspace = torch.empty(nw, dtype=torch.uint8, device=self.device)
+            if state is None:
+                self.state = torch.zeros(nb, dtype=torch.uint8, device=self.device)
+            else:
+                self.state = _caller_buffer(state, nb, self.device, "state").zero_()
+            if workspace is None:
+                self.workspace = torch.empty(nw, dtype=torch.uint8, device=self.device)
+            else:
+                self.workspace = _caller_buffer(workspace, nw, self.device, "workspace")
             self.stream = torch.cuda.current_stream(self.device)
             phi0 = _dev_f64(phi0, self.shape, self.device)
             ux0 = _dev_f64(ux0, self.shape, self.device)

@@ -465,3 +465,22 @@ def test_mrt_fused_and_two_kernel_paths_agree_bitwise(prec):
     b.step(30)
     for x, y in zip(gpu_state(a), gpu_state(b)):
         assert np.array_equal(x, y)
+
+
+def test_caller_provided_buffers_bitwise():
+    # a Sim on caller-provided (reused, dirty) state and workspace buffers
+    # gives the same bits as one on its own
+    from paper_2311_10827_amd.sim import Sim, make_params
+    wl = inputs.COALESCENCE
+    phi0 = inputs.two_drops(200, 130, 20.0, 5.0, noise=1e-3, workload_id=15)
+    p = make_params(wl, precision=32, nx=200, ny=130)
+    a = Sim(p, phi0)
+    st = torch.full((a.state.numel() + 4096,), 7, dtype=torch.uint8, device="cuda")
+    ws = torch.full((a.workspace.numel(),), 9, dtype=torch.uint8, device="cuda")
+    b = Sim(p, phi0, state=st, workspace=ws)
+    a.step(40)
+    b.step(40)
+    for x, y in zip(gpu_state(a), gpu_state(b)):
+        assert np.array_equal(x, y)
+    with pytest.raises(ValueError):
+        Sim(p, phi0, state=st[: a.state.numel() - 1])
