@@ -49,12 +49,13 @@ def workload(case: str, rho_ratio: float, mu_ratio: float | None = None) -> tupl
 
 
 def relax(case: str, rho_ratio: float, steps: int, every: int, mu_ratio: float | None = None,
-          precision: int = 64, kernel_path: int = 0, log=None):
+          precision: int = 64, kernel_path: int = 0, log=None, **over):
     """Run the case and return [(step, E, max|u|, mu spread)] every `every`
-    steps (E and max|u| from the library's FP64 diagnostics)."""
+    steps (E and max|u| from the library's FP64 diagnostics).  ``over``:
+    further lbm_params fields (a collision operator and its rates, say)."""
     from .sim import Sim, make_params
     wl, phi0 = workload(case, rho_ratio, mu_ratio)
-    sim = Sim(make_params(wl, precision=precision, kernel_path=kernel_path), phi0)
+    sim = Sim(make_params(wl, precision=precision, kernel_path=kernel_path, **over), phi0)
     hist = []
     try:
         done = 0

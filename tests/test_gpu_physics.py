@@ -95,3 +95,19 @@ def test_paper_flat_interface_relaxes_to_round_off():
     say(f"  min E {E:.3e} at step {step}, max|u| {umax:.3e}, mu spread {mu_spread:.3e}")
     assert E <= 1e-24
     assert umax <= 1e-14
+
+
+def test_paper_flat_interface_relaxes_to_round_off_under_mrt():
+    # The same slab with the MRT collision (free rates away from BGK's): the
+    # discrete equilibrium is still a fixed point, so the kinetic energy
+    # still falls to round-off.
+    from paper_2311_10827_amd.replica import relax
+    say("[gpu] paper flat interface, MRT, density ratio 1000, 1e6 steps")
+    hist = relax("flat", 1000.0, 1_000_000, 100_000, collision=1, mrt_f=(1.3, 1.1, 1.6, 1.4),
+                 mrt_g=(1.5, 1.7))
+    k = min(range(len(hist)), key=lambda i: hist[i][1])
+    step, E, umax, mu_spread = hist[k]
+    say(f"  min E {E:.3e} at step {step}, max|u| {umax:.3e}, mu spread {mu_spread:.3e}")
+    assert E <= 1e-24
+    assert umax <= 1e-14
+
