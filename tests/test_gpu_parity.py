@@ -484,3 +484,24 @@ def test_caller_provided_buffers_bitwise():
         assert np.array_equal(x, y)
     with pytest.raises(ValueError):
         Sim(p, phi0, state=st[: a.state.numel() - 1])
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_fp32_error_mrt_exp_viscosity_long_run(path):
+    # FP32 deviation storage under the MRT collision and the exponential
+    # viscosity law over 3000 steps of a walled two-drop field at density
+    # ratio 100: phi within 1e-5 and u within 1e-6 of the FP64 oracle
+    wl = inputs.Workload("mrt_long", 120, 64, bc_y=1, rho_A=100.0, rho_B=1.0, nu_A=0.01, nu_B=0.1,
+                         sigma=2e-3, W=4.0, M=0.05, nu_form=2, **MRT_RATES)
+    phi0 = inputs.two_drops(120, 64, 13.0, 3.0, noise=1e-3, workload_id=16)
+    say(f"[gpu] FP32 long run, MRT + exponential viscosity, kernel_path={path}")
+    o = oracle_sim(wl, phi0).step(3000)
+    g32 = gpu_sim(wl, phi0, 32, kernel_path=path)
+    g32.step(3000)
+    om = o.moments()
+    m32, d32 = gpu_moments(g32)
+    ephi = np.abs(m32["phi"] - om["phi"]).max()
+    eu = max(np.abs(m32["ux"] - om["ux"]).max(), np.abs(m32["uy"] - om["uy"]).max())
+    say(f"  phi err {ephi:.3e}  u err {eu:.3e}  max|u| {np.abs(om['ux']).max():.3e}")
+    assert d32["n_nonfinite"] == 0
+    assert ephi <= 1e-5 and eu <= 1e-6
