@@ -281,12 +281,16 @@ int lbm_step_into(lbm_ctx* ctx, void* src, void* dst);
  * (f_0..f_8, g_0..g_8, S_prev) in the storage precision (double for
  * precision 64, float for 32), device memory.  The arithmetic is in the
  * storage precision, like the forward step's; parameter gradients
- * accumulate in FP64.
+ * accumulate in FP64.  The adjoint follows the step the context was made
+ * for: either viscosity law (nu_form) and either collision (for MRT the
+ * moment-space relaxation M^-1 S M is symmetric, so its transpose is the
+ * same operator).
  *
  * Parameter gradients accumulate in the adjoint workspace for
  * theta = (kappa, beta, alpha, tau_f, nu_A, nu_B), each taken as independent
  * (tau_f = 1/2 + M/(c_s^2 alpha) and tau_g = 1/2 + nu/c_s^2 relate them to
- * M and the relaxation times).
+ * M and the relaxation times).  The MRT rates mrt_f, mrt_g are constants,
+ * not differentiated.
  * ---------------------------------------------------------------------- */
 
 /* Bytes of the adjoint workspace (7 planes plus parameter partials). */
