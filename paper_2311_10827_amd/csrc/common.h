@@ -120,8 +120,8 @@ __device__ __forceinline__ void mom_inv(const C (&m)[9], C (&v)[9]) {
   v[7] = dg - sx - sy + pxy;
   v[8] = dg + sx - sy - pxy;
 }
-// MRT relaxation: out = M^-1 (rate * (M d) + pre * (M b)) per moment; b may
-// be all zero (then pass has_b = false).
+// MRT relaxation, moment by moment: out = M^-1 (rate (M d) + (1 - rate/2) (M b));
+// with HAS_B false, b is not read and its term is left out.
 template <typename C, bool HAS_B>
 __device__ __forceinline__ void mrt_relax(const C (&rate)[9], const C (&d)[9], const C (&b)[9],
                                           C (&out)[9]) {
