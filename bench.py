@@ -27,13 +27,13 @@ METRIC = "MLUPS & % HBM roofline, FP32 vs FP64 step; adjoint/forward step cost r
 HBM_PEAK_GBPS = 8000.0
 # Algorithmic HBM bytes per lattice update (per cell) of the fused step
 # kernel, the only kernel of a step: every population plane read once and
-# written once (18 in FP64; 19 in FP32, where the rest population of f is a
-# hi + lo pair), the previous-step source read and the new one written.
-# phi and mu stay on chip.
-STEP_BYTES = {32: (19 + 19 + 1 + 1) * 4, 64: (18 + 18 + 1 + 1) * 8}
+# written once (18 in FP64; in FP32 18 words plus the 2-byte low word of the
+# rest population of f), the previous-step source read and the new one
+# written.  phi and mu stay on chip.
+STEP_BYTES = {32: 2 * (18 * 4 + 2 + 4), 64: (18 + 18 + 1 + 1) * 8}
 # The two-kernel path also writes phi and mu and reads them back, and reads
-# the f planes twice: +(2 + 2 + 10) * 4 B in FP32, +(2 + 2 + 9) * 8 B in FP64.
-TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (2 + 2 + 10) * 4, 64: STEP_BYTES[64] + (2 + 2 + 9) * 8}
+# the f planes twice: +(2 + 2) * 4 + 9 * 4 + 2 B in FP32, +(2 + 2 + 9) * 8 B in FP64.
+TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (2 + 2 + 9) * 4 + 2, 64: STEP_BYTES[64] + (2 + 2 + 9) * 8}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fused_many_drops_16384.json")
 
 

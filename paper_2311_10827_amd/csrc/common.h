@@ -6,9 +6,11 @@
 //   FP64: 18 planes  f_0..f_8, g_0..g_8
 //   FP32: 19 planes  f_0(hi), f_1..f_8, g_0..g_8, f_0(lo)
 // In FP32 the rest population of the order-parameter distribution is kept as
-// an unevaluated sum hi + lo of two FP32 numbers (minus phi_ref): it is of
-// order one and changes by far less than an FP32 ulp per step, so a single
-// FP32 word would drop those changes.  All other populations are small
+// an unevaluated sum hi + lo (minus phi_ref): it is of order one and changes
+// by far less than an FP32 ulp per step, so a single FP32 word would drop
+// those changes.  hi is an FP32 word; lo, never more than half an ulp of hi,
+// is a 16-bit multiple of ulp(hi)/2^16 in the first half of its plane (see
+// lo_encode).  All other populations are small
 // deviations from the rest equilibrium (g^eq(p=0, u=0) = 0, f^eq_i(mu=0) = 0
 // for i != 0) and keep full relative precision in one FP32 word.
 #pragma once
@@ -297,6 +299,30 @@ struct Pops {
   T lo;  // FP32 only: low word of f_0
 };
 
+// The low word of the FP32 rest population: lo = q ulp(hi) / 2^16 with q a
+// 16-bit integer (|lo| <= ulp(hi)/2 keeps |q| <= 2^15), which holds hi + lo
+// to about 2^-40 relative in 16 bits where an FP32 word takes 32.  For
+// |hi| < 2^-87 no low word is kept.
+__device__ __forceinline__ float lo_unit(float hi) {  // ulp(hi) / 2^16 = 2^(e - 166)
+  const unsigned e = (__float_as_uint(hi) >> 23) & 0xFFu;  // biased exponent of hi
+  return e > 39u ? __uint_as_float((e - 39u) << 23) : 0.0f;
+}
+__device__ __forceinline__ short lo_encode(float hi, float lo) {
+  const unsigned e = (__float_as_uint(hi) >> 23) & 0xFFu;
+  if (e <= 39u) return 0;
+  const float q = rintf(lo * __uint_as_float((293u - e) << 23));  // lo / unit, exact scaling
+  return (short)fminf(fmaxf(q, -32768.0f), 32767.0f);
+}
+__device__ __forceinline__ float lo_decode(float hi, short q) { return (float)q * lo_unit(hi); }
+template <typename T>
+__device__ __forceinline__ const short* lo_plane(const T* B, const KP& p) {
+  return reinterpret_cast<const short*>(B + LO_PLANE * p.ps);
+}
+template <typename T>
+__device__ __forceinline__ short* lo_plane(T* B, const KP& p) {
+  return reinterpret_cast<short*>(B + LO_PLANE * p.ps);
+}
+
 // WITH_G: also gather g.  WITH_F: gather f (and the low word of f_0);
 // WITH_F0 = false leaves out f_0 and its low word.
 // Offsets within a plane fit in 32 bits (pitch * ny <= INT32_MAX); the
@@ -323,7 +349,8 @@ __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int
       q.g[i] = pg[off];
     }
   }
-  if (WITH_F && WITH_F0 && std::is_same<T, float>::value) q.lo = (B + LO_PLANE * p.ps)[own];
+  if constexpr (WITH_F && WITH_F0 && std::is_same<T, float>::value)
+    q.lo = lo_decode(q.f[0], lo_plane(B, p)[own]);
 }
 
 // Store one pre-collision population so that the pull gather returns it:

@@ -316,7 +316,8 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
   const float wf = (float)p.omega_f;
   const float am = (float)p.alpha * mu;
   // f_0 - f_0^eq = -(s8 - (5/9) alpha mu) exactly, since phi = f_0 + s8; add the
-  // small increment to hi + lo (FastTwoSum keeps the rounding error in lo).
+  // small increment to hi + lo (TwoSum keeps the rounding error in lo, which
+  // then never exceeds half an ulp of hi).
   float corr_f[9];  // MRT: the correction to the BGK update
   if constexpr (MRT) {
     // f^eq_0 - f_0 = s8 - (5/9) alpha mu exactly (phi = f_0 + s8)
@@ -330,8 +331,9 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
   if constexpr (MRT) inc0 += corr_f[0];
   const float t = q.lo + inc0;
   const float hi = f[0] + t;
+  const float tv = hi - f[0];
   fo[0] = hi;
-  fo_lo = t - (hi - f[0]);
+  fo_lo = (f[0] - (hi - tv)) + (t - tv);
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
     fo[i] = f[i] + wf * ((float)w_of(i) * am - f[i]) + (float)(w_of(i) * src_bracket(i)) * src;
@@ -399,7 +401,7 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
         (Bout + i * p.ps)[o] = fo[i];
         (Bout + (9 + i) * p.ps)[o] = go[i];
       }
-      if constexpr (std::is_same<T, float>::value) (Bout + LO_PLANE * p.ps)[o] = lo;
+      if constexpr (std::is_same<T, float>::value) lo_plane(Bout, p)[o] = lo_encode(fo[0], lo);
       Spout[o] = (T)c.S;
     }
     if (MODE == M_INIT_S) Spout[o] = (T)c.S;
@@ -626,7 +628,7 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
         pop_store<NT>(fo[i], Bout + i * p.ps + o);
         pop_store<NT>(go[i], Bout + (9 + i) * p.ps + o);
       }
-      if constexpr (std::is_same<T, float>::value) pop_store<NT>(lo, Bout + LO_PLANE * p.ps + o);
+      if constexpr (std::is_same<T, float>::value) pop_store<NT>(lo_encode(fo[0], lo), lo_plane(Bout, p) + o);
       pop_store<NT>((T)c.S, Spout + o);
       if (DIAG) {
         const bool fin = isfinite(c.phi) && isfinite(c.mu) && isfinite(c.ux) && isfinite(c.uy) &&
@@ -667,7 +669,7 @@ __device__ __forceinline__ void put_f0(T* __restrict__ B, const KP& p, int x, in
     float hi, lo;
     split2(v, hi, lo);
     B[own] = hi;
-    B[LO_PLANE * p.ps + own] = lo;
+    lo_plane(B, p)[own] = lo_encode(hi, lo);
   } else {
     B[own] = v;
   }
