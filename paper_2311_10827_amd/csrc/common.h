@@ -9,8 +9,9 @@
 // an unevaluated sum hi + lo (minus phi_ref): it is of order one and changes
 // by far less than an FP32 ulp per step, so a single FP32 word would drop
 // those changes.  hi is an FP32 word; lo, never more than half an ulp of hi,
-// is a 16-bit multiple of ulp(hi)/2^16 in the first half of its plane (see
-// lo_encode).  All other populations are small
+// is an FP32 word or, for states larger than 1 GiB (the kernels' LO16
+// template argument), a 16-bit multiple of ulp(hi)/2^16 in the first half of
+// its plane (see lo_encode).  All other populations are small
 // deviations from the rest equilibrium (g^eq(p=0, u=0) = 0, f^eq_i(mu=0) = 0
 // for i != 0) and keep full relative precision in one FP32 word.
 #pragma once
@@ -324,11 +325,12 @@ __device__ __forceinline__ short* lo_plane(T* B, const KP& p) {
 }
 
 // WITH_G: also gather g.  WITH_F: gather f (and the low word of f_0);
-// WITH_F0 = false leaves out f_0 and its low word.
+// WITH_F0 = false leaves out f_0 and its low word.  LO16: the FP32 low word
+// is stored in 16 bits.
 // Offsets within a plane fit in 32 bits (pitch * ny <= INT32_MAX); the
 // plane of each load is one of two wave-uniform bases (the direction's own
 // or, for a bounce-back lane, the opposite one).
-template <bool WITH_G, typename T, bool WITH_F = true, bool WITH_F0 = true>
+template <bool WITH_G, typename T, bool WITH_F = true, bool WITH_F0 = true, bool LO16 = false>
 __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int x, int y, Pops<T>& q) {
   const PullCols px = pull_cols(x, p.nx, p.bcx);
   const PullCols py = pull_cols(y, p.ny, p.bcy);
@@ -349,8 +351,12 @@ __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int
       q.g[i] = pg[off];
     }
   }
-  if constexpr (WITH_F && WITH_F0 && std::is_same<T, float>::value)
-    q.lo = lo_decode(q.f[0], lo_plane(B, p)[own]);
+  if constexpr (WITH_F && WITH_F0 && std::is_same<T, float>::value) {
+    if constexpr (LO16)
+      q.lo = lo_decode(q.f[0], lo_plane(B, p)[own]);
+    else
+      q.lo = (B + LO_PLANE * p.ps)[own];
+  }
 }
 
 // Store one pre-collision population so that the pull gather returns it:

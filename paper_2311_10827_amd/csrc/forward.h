@@ -106,7 +106,7 @@ __device__ __forceinline__ C mu_cell(const KP& p, const C (&v)[3][3]) {
 // (initialisation); then the arithmetic is FP64 whatever the storage type.
 constexpr int K1_TX = 64, K1_TY = 16;
 
-template <typename T, bool FROM_INPUT>
+template <typename T, bool FROM_INPUT, bool LO16 = false>
 __global__ __launch_bounds__(256) void k_phi_mu(const KP p, const T* __restrict__ B,
                                                  const double* __restrict__ phi_in,
                                                  T* __restrict__ dphi_out, T* __restrict__ mu_out,
@@ -125,7 +125,7 @@ __global__ __launch_bounds__(256) void k_phi_mu(const KP p, const T* __restrict_
       v = (C)(phi_in[(long long)gy * p.nx + gx] - p.phi_ref);
     } else {
       Pops<T> q;
-      gather<false>(B, p, gx, gy, q);
+      gather<false, T, true, true, LO16>(B, p, gx, gy, q);
       v = (C)phi_sum<T>(q);
     }
     s[k] = v;
@@ -368,7 +368,7 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
 
 // Spin holds S_prev of the current step; Spout receives S (they may be the
 // same plane: each cell reads and then writes only its own entry).
-template <typename T, int MODE, bool MRT = false>
+template <typename T, int MODE, bool MRT = false, bool LO16 = false>
 __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bout, const T* Spin,
                                                   T* Spout, const T* __restrict__ dphi,
                                                   const T* __restrict__ mupl, MomOut mo,
@@ -384,7 +384,7 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
   if (valid) {
     const unsigned o = (unsigned)(y * p.pitch + x);
     Pops<T> q;
-    gather<true>(Bin, p, x, y, q);
+    gather<true, T, true, true, LO16>(Bin, p, x, y, q);
     Nbhd<T> nb;
     load_nbhd(p, dphi, mupl, x, y, nb);
     const T Sp = Spin[o];
@@ -401,7 +401,12 @@ __global__ __launch_bounds__(256) void k_collide(const KP p, const T* Bin, T* Bo
         (Bout + i * p.ps)[o] = fo[i];
         (Bout + (9 + i) * p.ps)[o] = go[i];
       }
-      if constexpr (std::is_same<T, float>::value) lo_plane(Bout, p)[o] = lo_encode(fo[0], lo);
+      if constexpr (std::is_same<T, float>::value) {
+        if constexpr (LO16)
+          lo_plane(Bout, p)[o] = lo_encode(fo[0], lo);
+        else
+          (Bout + LO_PLANE * p.ps)[o] = lo;
+      }
       Spout[o] = (T)c.S;
     }
     if (MODE == M_INIT_S) Spout[o] = (T)c.S;
@@ -491,8 +496,9 @@ __device__ __forceinline__ void pop_store(T v, T* ptr) {
 
 // NT: streaming population stores, for states larger than the last-level
 // cache (nothing reads them before they leave it); ordinary stores when the
-// state fits there, so that the next step finds them in it.
-template <typename T, int MODE, bool WRITE_PHIMU, bool MRT = false, bool NT = true>
+// state fits there, so that the next step finds them in it.  LO16: the FP32
+// low word of f_0 in 16 bits.
+template <typename T, int MODE, bool WRITE_PHIMU, bool MRT = false, bool NT = true, bool LO16 = false>
 __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T* Bin, T* Bout, const T* Spin,
                                                              T* Spout, T* __restrict__ dphi_out,
                                                              T* __restrict__ mu_out,
@@ -518,8 +524,8 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
   };
   auto phi_load = [&](int yu, PhiCols& L) {
     const int gy = stencil_idx(yu, p.ny, p.bcy);
-    gather<false>(Bin, p, stencil_idx(x0 - 2 + t, p.nx, p.bcx), gy, L.a);
-    if (t < 4) gather<false>(Bin, p, stencil_idx(x0 - 2 + W + t, p.nx, p.bcx), gy, L.b);
+    gather<false, T, true, true, LO16>(Bin, p, stencil_idx(x0 - 2 + t, p.nx, p.bcx), gy, L.a);
+    if (t < 4) gather<false, T, true, true, LO16>(Bin, p, stencil_idx(x0 - 2 + W + t, p.nx, p.bcx), gy, L.b);
   };
   // phi of row yu (unwrapped) into the ring; for rows this strip collides
   // the gathered f of its own columns is kept for the collision.
@@ -628,7 +634,12 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
         pop_store<NT>(fo[i], Bout + i * p.ps + o);
         pop_store<NT>(go[i], Bout + (9 + i) * p.ps + o);
       }
-      if constexpr (std::is_same<T, float>::value) pop_store<NT>(lo_encode(fo[0], lo), lo_plane(Bout, p) + o);
+      if constexpr (std::is_same<T, float>::value) {
+        if constexpr (LO16)
+          pop_store<NT>(lo_encode(fo[0], lo), lo_plane(Bout, p) + o);
+        else
+          pop_store<NT>(lo, Bout + LO_PLANE * p.ps + o);
+      }
       pop_store<NT>((T)c.S, Spout + o);
       if (DIAG) {
         const bool fin = isfinite(c.phi) && isfinite(c.mu) && isfinite(c.ux) && isfinite(c.uy) &&
@@ -661,7 +672,7 @@ __global__ __launch_bounds__(256) void k_reduce_diag(const double* __restrict__ 
 }
 
 // ------------------------------------------------------------ state I/O
-template <typename T>
+template <typename T, bool LO16>
 __device__ __forceinline__ void put_f0(T* __restrict__ B, const KP& p, int x, int y, double v) {
   // the rest population never streams, so it is stored at the cell itself
   const long long own = (long long)y * p.pitch + x;
@@ -669,7 +680,10 @@ __device__ __forceinline__ void put_f0(T* __restrict__ B, const KP& p, int x, in
     float hi, lo;
     split2(v, hi, lo);
     B[own] = hi;
-    lo_plane(B, p)[own] = lo_encode(hi, lo);
+    if constexpr (LO16)
+      lo_plane(B, p)[own] = lo_encode(hi, lo);
+    else
+      B[LO_PLANE * p.ps + own] = lo;
   } else {
     B[own] = v;
   }
@@ -678,7 +692,7 @@ __device__ __forceinline__ void put_f0(T* __restrict__ B, const KP& p, int x, in
 // Initial populations (time 0): f = f^eq(phi0, mu0) (Sec. 2.3.1, eq. H_i) and
 // g = g^eq(p = 0, u0) (Sec. 2.3.2, eqs. G_i, Siu), in FP64; mu0 comes from
 // k_phi_mu<FROM_INPUT>.
-template <typename T>
+template <typename T, bool LO16 = false>
 __global__ __launch_bounds__(256) void k_init_pops(const KP p, T* __restrict__ B,
                                                     const double* __restrict__ phi0,
                                                     const double* __restrict__ ux0,
@@ -689,7 +703,7 @@ __global__ __launch_bounds__(256) void k_init_pops(const KP p, T* __restrict__ B
   const int y = (int)(k / p.nx), x = (int)(k - (long long)y * p.nx);
   const double ph = phi0[k];
   const double mu = (double)mupl[(long long)y * p.pitch + x];
-  put_f0<T>(B, p, x, y, (ph - ((1.0 - w_of(0)) * p.alpha) * mu) - p.phi_ref);
+  put_f0<T, LO16>(B, p, x, y, (ph - ((1.0 - w_of(0)) * p.alpha) * mu) - p.phi_ref);
   for (int i = 1; i < 9; ++i) scatter<T>(B, p, x, y, 0, i, (T)((w_of(i) * p.alpha) * mu));
   const double ux = ux0 ? ux0[k] : 0.0, uy = uy0 ? uy0[k] : 0.0;
   const double rho = p.rhoB + (ph - p.phiB) * p.rho_slope;
@@ -697,7 +711,7 @@ __global__ __launch_bounds__(256) void k_init_pops(const KP p, T* __restrict__ B
   for (int i = 0; i < 9; ++i) scatter<T>(B, p, x, y, 9, i, (T)(rho * s_f64(i, ux, uy, uu)));
 }
 
-template <typename T>
+template <typename T, bool LO16 = false>
 __global__ __launch_bounds__(256) void k_set_state(const KP p, T* __restrict__ B, T* __restrict__ Spl,
                                                     const double* __restrict__ f,
                                                     const double* __restrict__ g,
@@ -706,13 +720,13 @@ __global__ __launch_bounds__(256) void k_set_state(const KP p, T* __restrict__ B
   const long long n = (long long)p.nx * p.ny;
   if (k >= n) return;
   const int y = (int)(k / p.nx), x = (int)(k - (long long)y * p.nx);
-  put_f0<T>(B, p, x, y, f[k] - p.phi_ref);
+  put_f0<T, LO16>(B, p, x, y, f[k] - p.phi_ref);
   for (int i = 1; i < 9; ++i) scatter<T>(B, p, x, y, 0, i, (T)f[i * n + k]);
   for (int i = 0; i < 9; ++i) scatter<T>(B, p, x, y, 9, i, (T)g[i * n + k]);
   Spl[(long long)y * p.pitch + x] = (T)Sp[k];
 }
 
-template <typename T>
+template <typename T, bool LO16 = false>
 __global__ __launch_bounds__(256) void k_get_state(const KP p, const T* __restrict__ B,
                                                     const T* __restrict__ Spl, int x0, int y0,
                                                     int w, int h, double* __restrict__ f,
@@ -724,7 +738,7 @@ __global__ __launch_bounds__(256) void k_get_state(const KP p, const T* __restri
   const int wy = (int)(k / w), wx = (int)(k - (long long)wy * w);
   const int x = (x0 + wx) % p.nx, y = (y0 + wy) % p.ny;
   Pops<T> q;
-  gather<true>(B, p, x, y, q);
+  gather<true, T, true, true, LO16>(B, p, x, y, q);
   if (f) {
     double f0 = (double)q.f[0];
     if constexpr (std::is_same<T, float>::value) f0 = f0 + (double)q.lo;

@@ -38,6 +38,7 @@ struct lbm_ctx {
   int ntx1, nty1, ntx2, nty2;
   int ntxf, ntyf, hf;   // strips of the fused step kernel and their height
   bool fused_nt;        // the fused step stores streaming (state above the cache size)
+  bool lo16;            // FP32: the low word of f_0 in 16 bits (state above LO16_STATE_BYTES)
   int ntxm, ntym;       // tiles of ka_mu_phi (no more than the K2 tiles, whose
                         // count sizes the parameter partials)
   bool fused;           // lbm_step runs the fused kernel
@@ -124,9 +125,13 @@ constexpr long long FUSED_MIN_BLOCKS = 2048;
 // kernel_path 0 runs the fused step when the grid gives at least this many
 // strips of 256 x 8 cells
 constexpr long long FUSED_AUTO_STRIPS_32 = 512, FUSED_AUTO_STRIPS_64 = 512;
-// the fused step stores streaming above this state size (MI355X has a
-// 256 MB last-level cache; a state that fits is read back from it)
+// above this state size the fused step stores streaming (MI355X has a 256 MB
+// last-level cache; a state that fits is read back from it)
 constexpr size_t FUSED_CACHED_STATE_BYTES = (size_t)224 << 20;
+// above this FP32 state size the low word of f_0 is kept in 16 bits: 2 % off
+// the HBM-bound step from 4096^2 up, 3 % on at 2048^2 where its arithmetic
+// is not hidden
+constexpr size_t LO16_STATE_BYTES = (size_t)1 << 30;
 
 size_t adj_plane_bytes(const lbm_params* p) {
   return round_up((size_t)p->nx * p->ny * (p->precision == 32 ? 4 : 8), 256);
@@ -183,13 +188,31 @@ T* mu_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + 2); }
 
 unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
+// The kernels that read or write the FP32 low word of f_0 take its format as
+// a template argument (LO16); f is called with std::true_type for an FP32
+// context that keeps it in 16 bits, else with std::false_type.
+template <typename T, typename F>
+void lo_dispatch(const lbm_ctx* c, F&& f) {
+  if (std::is_same<T, float>::value && c->lo16)
+    f(std::true_type{});
+  else
+    f(std::false_type{});
+}
+
 // A "state" is a pop buffer (NB planes) plus an S_prev plane.  The context's
 // own state is its current pop buffer with the shared S plane; a snapshot
 // holds NB + 1 consecutive planes in the same layout.
 template <typename T>
+void launch_phi_mu_k(lbm_ctx* c, const T* B, T* dphi, T* mu) {
+  lo_dispatch<T>(c, [&](auto lo) {
+    constexpr bool L16 = decltype(lo)::value && std::is_same<T, float>::value;
+    hipLaunchKernelGGL((k_phi_mu<T, false, L16>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp,
+                       B, nullptr, dphi, mu, c->ntx1);
+  });
+}
+template <typename T>
 int launch_phi_mu(lbm_ctx* c, const T* B) {
-  hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, B,
-                     nullptr, dphi_plane<T>(c), mu_plane<T>(c), c->ntx1);
+  launch_phi_mu_k<T>(c, B, dphi_plane<T>(c), mu_plane<T>(c));
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -203,12 +226,15 @@ template <typename T, int MODE>
 int launch_collide(lbm_ctx* c, MomOut mo, const T* Bin, T* Bout, const T* Sin, T* Sout, const T* dphi,
                    const T* mu) {
   constexpr bool COLLIDES = MODE == M_STEP || MODE == M_STEP_DIAG;
-  if (COLLIDES && c->kp.collision == LBM_MRT)
-    hipLaunchKernelGGL((k_collide<T, MODE, COLLIDES>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream,
-                       c->kp, Bin, Bout, Sin, Sout, dphi, mu, mo, c->partials, c->ntx2);
-  else
-    hipLaunchKernelGGL((k_collide<T, MODE>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream, c->kp,
-                       Bin, Bout, Sin, Sout, dphi, mu, mo, c->partials, c->ntx2);
+  lo_dispatch<T>(c, [&](auto lo) {
+    constexpr bool L16 = decltype(lo)::value && std::is_same<T, float>::value;
+    if (COLLIDES && c->kp.collision == LBM_MRT)
+      hipLaunchKernelGGL((k_collide<T, MODE, COLLIDES, L16>), dim3(c->ntx2 * c->nty2), dim3(256), 0,
+                         c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, mo, c->partials, c->ntx2);
+    else
+      hipLaunchKernelGGL((k_collide<T, MODE, false, L16>), dim3(c->ntx2 * c->nty2), dim3(256), 0, c->stream,
+                         c->kp, Bin, Bout, Sin, Sout, dphi, mu, mo, c->partials, c->ntx2);
+  });
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -224,8 +250,12 @@ int launch_collide(lbm_ctx* c, MomOut mo) {
 
 template <typename T, int MODE, bool WRITE_PHIMU, bool MRT, bool NT>
 void launch_fused_k(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
-  hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU, MRT, NT>), dim3(c->ntxf * c->ntyf), dim3(Strip<T>::W),
-                     0, c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials, c->ntxf, c->hf);
+  lo_dispatch<T>(c, [&](auto lo) {
+    constexpr bool L16 = decltype(lo)::value && std::is_same<T, float>::value;
+    hipLaunchKernelGGL((k_step_fused<T, MODE, WRITE_PHIMU, MRT, NT, L16>), dim3(c->ntxf * c->ntyf),
+                       dim3(Strip<T>::W), 0, c->stream, c->kp, Bin, Bout, Sin, Sout, dphi, mu, c->partials,
+                       c->ntxf, c->hf);
+  });
 }
 template <typename T, int MODE, bool WRITE_PHIMU>
 int launch_fused(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dphi, T* mu) {
@@ -349,8 +379,11 @@ int init_impl(lbm_ctx* c, const double* phi0, const double* ux0, const double* u
                      nullptr, phi0, dphi_plane<T>(c), mu_plane<T>(c), c->ntx1);
   LAUNCHCHK(c);
   const long long n = (long long)c->p.nx * c->p.ny;
-  hipLaunchKernelGGL(k_init_pops<T>, dim3(blocks_for(n)), dim3(256), 0, c->stream, c->kp,
-                     popbuf<T>(c, c->cur), phi0, ux0, uy0, mu_plane<T>(c));
+  lo_dispatch<T>(c, [&](auto lo) {
+    constexpr bool L16 = decltype(lo)::value && std::is_same<T, float>::value;
+    hipLaunchKernelGGL((k_init_pops<T, L16>), dim3(blocks_for(n)), dim3(256), 0, c->stream, c->kp,
+                       popbuf<T>(c, c->cur), phi0, ux0, uy0, mu_plane<T>(c));
+  });
   LAUNCHCHK(c);
   int r = launch_phi_mu<T>(c);
   if (r) return r;
@@ -377,8 +410,11 @@ int moments_impl(lbm_ctx* c, MomOut mo, lbm_diag* diag) {
 template <typename T>
 int get_state_impl(lbm_ctx* c, int x0, int y0, int w, int h, double* f, double* g, double* Sp) {
   const long long n = (long long)w * h;
-  hipLaunchKernelGGL(k_get_state<T>, dim3(blocks_for(n)), dim3(256), 0, c->stream, c->kp,
-                     popbuf<T>(c, c->cur), S_plane<T>(c), x0, y0, w, h, f, g, Sp);
+  lo_dispatch<T>(c, [&](auto lo) {
+    constexpr bool L16 = decltype(lo)::value && std::is_same<T, float>::value;
+    hipLaunchKernelGGL((k_get_state<T, L16>), dim3(blocks_for(n)), dim3(256), 0, c->stream, c->kp,
+                       popbuf<T>(c, c->cur), S_plane<T>(c), x0, y0, w, h, f, g, Sp);
+  });
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -386,8 +422,11 @@ int get_state_impl(lbm_ctx* c, int x0, int y0, int w, int h, double* f, double* 
 template <typename T>
 int set_state_impl(lbm_ctx* c, const double* f, const double* g, const double* Sp) {
   const long long n = (long long)c->p.nx * c->p.ny;
-  hipLaunchKernelGGL(k_set_state<T>, dim3(blocks_for(n)), dim3(256), 0, c->stream, c->kp,
-                     popbuf<T>(c, c->cur), S_plane<T>(c), f, g, Sp);
+  lo_dispatch<T>(c, [&](auto lo) {
+    constexpr bool L16 = decltype(lo)::value && std::is_same<T, float>::value;
+    hipLaunchKernelGGL((k_set_state<T, L16>), dim3(blocks_for(n)), dim3(256), 0, c->stream, c->kp,
+                       popbuf<T>(c, c->cur), S_plane<T>(c), f, g, Sp);
+  });
   LAUNCHCHK(c);
   return LBM_OK;
 }
@@ -421,8 +460,7 @@ int step_into_impl(lbm_ctx* c, T* src, T* dst) {
   if (c->fused)
     return launch_fused<T, M_STEP, true>(c, src, dst, snap_S(c, src), snap_S(c, dst), snap_dphi(c, src),
                                          snap_mu(c, src));
-  hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, src,
-                     nullptr, snap_dphi(c, src), snap_mu(c, src), c->ntx1);
+  launch_phi_mu_k<T>(c, src, snap_dphi(c, src), snap_mu(c, src));
   LAUNCHCHK(c);
   return launch_collide<T, M_STEP>(c, MomOut{}, src, dst, snap_S(c, src), snap_S(c, dst),
                                   snap_dphi(c, src), snap_mu(c, src));
@@ -433,8 +471,7 @@ int adjoint_step_impl(lbm_ctx* c, T* state, const T* lam_in, T* lam_out, bool ha
   T* dphi = snap_dphi(c, state);
   T* mu = snap_mu(c, state);
   if (!have_phi_mu) {
-    hipLaunchKernelGGL((k_phi_mu<T, false>), dim3(c->ntx1 * c->nty1), dim3(256), 0, c->stream, c->kp, state,
-                       nullptr, dphi, mu, c->ntx1);
+    launch_phi_mu_k<T>(c, state, dphi, mu);
     LAUNCHCHK(c);
   }
   const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
@@ -614,6 +651,9 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   k.collision = p->collision;
   for (int i = 0; i < 4; ++i) k.mf[i] = p->mrt_f[i];
   for (int i = 0; i < 2; ++i) k.mg[i] = p->mrt_g[i];
+  // the 16-bit low word of f_0 pays where the step is bound by HBM; on
+  // smaller states its arithmetic costs more than the bytes it saves
+  c->lo16 = p->precision == 32 && L.state_bytes > LO16_STATE_BYTES;
   hipError_t e = hipHostMalloc((void**)&c->diag_host, 2 * NQ * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;

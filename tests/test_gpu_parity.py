@@ -505,3 +505,44 @@ def test_fp32_error_mrt_exp_viscosity_long_run(path):
     say(f"  phi err {ephi:.3e}  u err {eu:.3e}  max|u| {np.abs(om['ux']).max():.3e}")
     assert d32["n_nonfinite"] == 0
     assert ephi <= 1e-5 and eu <= 1e-6
+
+
+# FP32 states beyond the last-level cache: 2048 x 1024 (328 MiB: streaming
+# stores, FP32 low word of f_0) and 4096 x 1700 (1.14 GB: streaming stores,
+# 16-bit low word)
+_BIG = {"2048x1024": (2048, 1024, 150.0, False), "4096x1700": (4096, 1700, 250.0, True)}
+_BIG_STEPS = 60
+
+
+def _big_wl(nx, ny):
+    return inputs.Workload(f"big_fp32_{nx}x{ny}", nx, ny, bc_y=1, rho_A=10.0, rho_B=1.0, nu_A=0.05,
+                           nu_B=0.1, sigma=5e-3, W=4.0, M=0.05)
+
+
+@pytest.fixture(scope="module", params=list(_BIG))
+def big_oracle(request):
+    nx, ny, R, lo16 = _BIG[request.param]
+    wl = _big_wl(nx, ny)
+    phi0 = inputs.two_drops(nx, ny, R, 4.0, noise=1e-3, workload_id=17)
+    say(f"[oracle] {nx}x{ny}, {_BIG_STEPS} steps")
+    return wl, lo16, phi0, oracle_sim(wl, phi0).step(_BIG_STEPS).moments()
+
+
+@pytest.mark.parametrize("path", PATHS)
+def test_fp32_state_beyond_cache_against_oracle(path, big_oracle):
+    # a walled two-drop field against the FP64 oracle, to the FP32 bounds
+    import ctypes
+    from paper_2311_10827_amd import _lib
+    from paper_2311_10827_amd.sim import make_params
+    wl, lo16, phi0, om = big_oracle
+    nb = _lib.load().lbm_state_bytes(ctypes.byref(make_params(wl, precision=32)))
+    assert nb > (224 << 20) and (nb > (1 << 30)) == lo16
+    say(f"[gpu] FP32 {wl.nx}x{wl.ny} (16-bit low word: {lo16}), kernel_path={path}, {_BIG_STEPS} steps")
+    g32 = gpu_sim(wl, phi0, 32, kernel_path=path)
+    g32.step(_BIG_STEPS)
+    m32, d32 = gpu_moments(g32)
+    ephi = np.abs(m32["phi"] - om["phi"]).max()
+    eu = max(np.abs(m32["ux"] - om["ux"]).max(), np.abs(m32["uy"] - om["uy"]).max())
+    say(f"  phi err {ephi:.3e}  u err {eu:.3e}  max|u| {np.abs(om['ux']).max():.3e}")
+    assert d32["n_nonfinite"] == 0
+    assert ephi <= 1e-5 and eu <= 1e-6
