@@ -78,9 +78,10 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
  *   precision      64: populations stored and updated in FP64.
  *                  32: populations stored and updated in FP32; the rest
  *                      population of f, of order one, is held as an
- *                      unevaluated pair hi + lo (an FP32 word and a 16-bit
- *                      fraction of ulp(hi), about 2^-40 relative) offset by
- *                      (phi_A + phi_B) / 2, the others are small deviations
+ *                      unevaluated pair hi + lo (FP32 words; for states
+ *                      above 1 GiB lo is a 16-bit fraction of ulp(hi), about
+ *                      2^-40 relative) offset by (phi_A + phi_B) / 2, the
+ *                      others are small deviations
  *                      from the rest equilibrium; diagnostics stay FP64.
  *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
  *                  diagnostic pass every k steps (see lbm_step).
