@@ -471,13 +471,17 @@ struct Strip;
 // FR: rows in the LDS ring of the strip's gathered f.  Four rows (FP32, 40
 // KiB) need no barrier beyond the two per row; three rows (FP64, 54 KiB, so
 // that two workgroups fit a CU) need one more per row.
+// H = 32: against 64-row strips, 1-2 % faster at 8192^2 and 16384^2 in both
+// precisions on every allocation measured, although the f halo rows read
+// per strip double; 16 and 24 rows are slower again, and much taller
+// strips (up to one band of workgroups per column) slower still.
 template <>
 struct Strip<float> {
-  static constexpr int W = 256, H = 64, FR = 4;
+  static constexpr int W = 256, H = 32, FR = 4;
 };
 template <>
 struct Strip<double> {
-  static constexpr int W = 256, H = 64, FR = 3;
+  static constexpr int W = 256, H = 32, FR = 3;
 };
 
 __device__ __forceinline__ int mod_pos(int a, int m) {
