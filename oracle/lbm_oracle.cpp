@@ -24,7 +24,7 @@
 //  11. streaming (periodic, or half-way bounce-back walls)
 //  12. keep S for the next step's time derivative of F_i
 //
-// Readings where the paper is silent or garbled (listed in the design doc):
+// Readings where the paper is silent or garbled:
 //  * c_s^2 = 1/3, delta_x = delta_t = 1 (the text's "c/sqrt(3)" is garbled).
 //  * The time derivative in eq. BGK is the first-order backward difference
 //    [F_i(t) - F_i(t-1)]/delta_t, which needs S of the previous step.
