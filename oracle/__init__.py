@@ -212,6 +212,17 @@ def gradient(prm: Params, field):
     return gx, gy
 
 
+def divergence(prm: Params, ux, uy):
+    """Discrete divergence of a velocity field, d_x u_x + d_y u_y, each
+    derivative the isotropic gradient of Sec. 2.3.2 (eq. gradient) with the
+    grid's periodic wrap or mirrored wall ghosts.  The equations the model
+    recovers are incompressible (Sec. 2.3.2), so max |div u| measures how far
+    the lattice velocity is from divergence-free."""
+    gxx, _ = gradient(prm, ux)
+    _, gyy = gradient(prm, uy)
+    return gxx + gyy
+
+
 def laplacian(prm: Params, field):
     field = _f64(field, (prm.ny, prm.nx))
     out = np.zeros_like(field)

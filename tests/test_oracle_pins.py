@@ -65,6 +65,62 @@ def test_stencil_fourier_symbols(m, n):
     assert np.abs(lap - sym * np.cos(th)).max() < 1e-14
 
 
+@pytest.mark.parametrize("m,n,a,b", [(1, 0, 0, 1), (3, 1, 2, 5), (2, 5, 7, 3)])
+def test_divergence_fourier_symbol(m, n, a, b):
+    # d_x u_x + d_y u_y of two plane waves on a periodic grid, each
+    # derivative with the exact symbol of the isotropic gradient (Sec. 2.3.2,
+    # eq. gradient): d_x cos(th) = -sin(kx) (2/3 + cos(ky)/3) sin(th).
+    nx, ny = 16, 12
+    prm = oracle.Params(nx=nx, ny=ny)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    k1 = (2 * np.pi * m / nx, 2 * np.pi * n / ny)
+    k2 = (2 * np.pi * a / nx, 2 * np.pi * b / ny)
+    th1 = k1[0] * X + k1[1] * Y + 0.3
+    th2 = k2[0] * X + k2[1] * Y - 1.1
+    ux, uy = 0.7 * np.cos(th1), -0.4 * np.cos(th2)
+    want = (-0.7 * np.sin(k1[0]) * (2.0 / 3 + np.cos(k1[1]) / 3) * np.sin(th1)
+            + 0.4 * np.sin(k2[1]) * (2.0 / 3 + np.cos(k2[0]) / 3) * np.sin(th2))
+    assert np.abs(oracle.divergence(prm, ux, uy) - want).max() < 1e-14
+
+
+def test_discrete_curl_is_divergence_free():
+    # Both stencils are shift-invariant on a periodic grid, so they commute:
+    # u = (D_y psi, -D_x psi) has D_x u_x + D_y u_y = 0 up to rounding, for
+    # any psi.  A swapped component or sign in the divergence breaks this.
+    rng = np.random.default_rng(5)
+    prm = oracle.Params(nx=17, ny=11)
+    psi = rng.standard_normal((11, 17))
+    gx, gy = oracle.gradient(prm, psi)
+    assert np.abs(oracle.divergence(prm, gy, -gx)).max() < 1e-15
+    assert np.abs(oracle.divergence(prm, gx, gy)).max() > 0.1
+
+
+def test_divergence_of_a_prescribed_velocity_state():
+    # A uniform bulk phase (mu = 0, so no interfacial force) whose g is the
+    # equilibrium g^eq(p = 0, u) of a prescribed velocity field (Sec. 2.3.2,
+    # eqs. G_i, Siu): the recovered velocity is that field, and its
+    # divergence the closed form of the plane waves.
+    nx, ny = 16, 12
+    prm = oracle.Params(nx=nx, ny=ny, rho_A=3.0, rho_B=1.0)
+    X, Y = np.meshgrid(np.arange(nx), np.arange(ny))
+    kx, ky = 2 * np.pi * 2 / nx, 2 * np.pi * 1 / ny
+    ux = 1e-3 * np.sin(kx * X)
+    uy = -2e-3 * np.cos(ky * Y)
+    rho = prm.rho_A
+    f = np.zeros((9, ny, nx))
+    g = np.zeros((9, ny, nx))
+    f[:] = oracle.feq(prm, prm.phi_A, 0.0)[:, None, None]
+    for j in range(ny):
+        for i in range(nx):
+            g[:, j, i] = oracle.geq(prm, 0.0, rho, ux[j, i], uy[j, i])
+    o = oracle.Sim(prm)
+    o.set_state(f, g, np.zeros((ny, nx)))
+    m = o.moments()
+    assert np.abs(m["ux"] - ux).max() < 1e-17 and np.abs(m["uy"] - uy).max() < 1e-17
+    want = 1e-3 * np.sin(kx) * np.cos(kx * X) + 2e-3 * np.sin(ky) * np.sin(ky * Y)
+    assert np.abs(oracle.divergence(prm, m["ux"], m["uy"]) - want).max() < 1e-17
+
+
 def test_stencils_exact_on_polynomials_interior():
     # Second-order stencils are exact on linear (gradient) and quadratic
     # (Laplacian) fields away from walls.
