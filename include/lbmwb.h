@@ -163,6 +163,12 @@ typedef struct lbm_diag {
   double min_rho, max_rho;
   double mu_min, mu_max;
   double phi_min, phi_max;
+  double max_div_u;       /* max_x |d_x u_x + d_y u_y|, each derivative the
+                           * isotropic gradient of Sec. 2.3.2 (eq. gradient)
+                           * with the stencils' wrap or mirrored wall ghosts;
+                           * the recovered equations are incompressible.
+                           * Formed by lbm_moments only: -1 from
+                           * lbm_last_diag */
   int64_t n_nonfinite;    /* cells whose phi, mu, u or p is not finite */
   int64_t step;
 } lbm_diag;
@@ -216,8 +222,11 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
 /*
  * Moments of the current pre-collision state: phi, mu, ux, uy, p, rho.
  * Each output is device FP64 [ny][nx] or NULL.  If diag is not NULL it
- * receives the diagnostics (host struct); that makes the call synchronise
- * the stream.  Does not advance time.
+ * receives the diagnostics (host struct), max_div_u included; that makes
+ * the call synchronise the stream.  With diag and a NULL ux or uy, the
+ * velocity is staged in the state's idle population buffer (the one the
+ * next step overwrites), so no memory beyond the state is needed.  Does
+ * not advance time.
  */
 int lbm_moments(lbm_ctx* ctx, double* phi, double* mu, double* ux, double* uy, double* p,
                 double* rho, lbm_diag* diag);

@@ -664,6 +664,56 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
   if (DIAG) block_reduce_write(dg, partials + (long long)blk * NQ);
 }
 
+// Maximum of v over the 256 lanes of a block (every lane gets it).
+__device__ __forceinline__ double block_max256(double v) {
+  __shared__ double red[4];
+  for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  const double m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+  __syncthreads();
+  return m;
+}
+
+// max_x |div u| in FP64, first pass: div u = d_x u_x + d_y u_y, each
+// derivative the isotropic gradient of Sec. 2.3.2 (eq. gradient), with the
+// stencils' periodic wrap or mirrored wall ghosts, over dense velocity
+// planes [ny][nx].  Block b takes cells b*256 + t, stepping by the whole
+// grid, and writes its maximum to part[b]; non-finite values are left out
+// (the non-finite count of the diagnostics reports them).
+__global__ __launch_bounds__(256) void k_max_div_u(const KP p, const double* __restrict__ ux,
+                                                    const double* __restrict__ uy,
+                                                    double* __restrict__ part) {
+  const long long n = (long long)p.nx * p.ny;
+  double m = 0.0;
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const int y = (int)(k / p.nx), x = (int)(k - (long long)y * p.nx);
+    double dx = 0.0, dy = 0.0;
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const long long kn = (long long)stencil_idx(y + cy_of(i), p.ny, p.bcy) * p.nx +
+                           stencil_idx(x + cx_of(i), p.nx, p.bcx);
+      if (cx_of(i) != 0) dx = dx + ((w_of(i) * cx_of(i)) * ux[kn]) * INV_CS2;
+      if (cy_of(i) != 0) dy = dy + ((w_of(i) * cy_of(i)) * uy[kn]) * INV_CS2;
+    }
+    const double d = fabs(dx + dy);
+    if (isfinite(d)) m = fmax(m, d);
+  }
+  m = block_max256(m);
+  if (threadIdx.x == 0) part[blockIdx.x] = m;
+}
+
+// Second pass: the maximum of n partials into out[0] (one block).  A
+// maximum does not depend on the order it is taken in.
+__global__ __launch_bounds__(256) void k_max_reduce(const double* __restrict__ part, int n,
+                                                     double* __restrict__ out) {
+  double m = 0.0;
+  for (int k = threadIdx.x; k < n; k += blockDim.x) m = fmax(m, part[k]);
+  m = block_max256(m);
+  if (threadIdx.x == 0) out[0] = m;
+}
+
 __global__ __launch_bounds__(256) void k_reduce_diag(const double* __restrict__ partials, long long n,
                                                       long long chunk, double* __restrict__ out) {
   Diag d;

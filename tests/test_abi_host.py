@@ -22,6 +22,27 @@ def test_header_and_binding_agree():
     assert declared_functions() == sorted(_lib.SYMBOLS)
 
 
+def declared_struct_fields(name):
+    """Field names of `typedef struct name {...}` in the header, in order."""
+    txt = re.sub(r"/\*.*?\*/", "", open(HEADER).read(), flags=re.S)
+    body = re.search(r"typedef struct %s \{(.*?)\}" % name, txt, flags=re.S).group(1)
+    out = []
+    for decl in body.split(";"):
+        decl = decl.strip()
+        if not decl:
+            continue
+        names = decl.split(None, 1)[1]
+        out += [re.sub(r"\[.*\]", "", v).strip() for v in names.split(",")]
+    return out
+
+
+@pytest.mark.parametrize("c_name,py_struct", [("lbm_params", _lib.LbmParams),
+                                               ("lbm_derived", _lib.LbmDerived),
+                                               ("lbm_diag", _lib.LbmDiag)])
+def test_structs_mirror_the_header(c_name, py_struct):
+    assert declared_struct_fields(c_name) == [f for f, _ in py_struct._fields_]
+
+
 def test_library_exports_every_symbol():
     L = _lib.load()
     for name in declared_functions():

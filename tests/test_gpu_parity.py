@@ -278,6 +278,48 @@ def test_diagnostics_match_oracle_moments_and_budget():
     assert abs(d1["sum_phi"] - (s0 - d["source_sum"])) <= 1e-13 * np.abs(om["phi"]).sum()
 
 
+@pytest.mark.parametrize("bc_x,kernel_path", [(0, 1), (1, 1), (0, 2), (1, 2)])
+def test_max_div_u_matches_oracle(bc_x, kernel_path):
+    # max |div u| of lbm_moments against the oracle's divergence of its own
+    # velocity (FP64 and FP32), with the velocity planes passed in and with
+    # none (staged in the idle population buffer, which must not disturb the
+    # next step); lbm_last_diag reports -1 for it.
+    import ctypes
+    from paper_2311_10827_amd._lib import LbmDiag
+    wl = inputs.ADJOINT
+    nx, ny = 150, 101
+    phi0 = inputs.two_drops(nx, ny, 25.0, 5.0, noise=1e-3)
+    say(f"[gpu] max |div u|, bc_x={bc_x}, kernel_path={kernel_path}")
+    o = oracle_sim(wl, phi0, nx=nx, ny=ny, bc_x=bc_x)
+    o.step(40)
+    om = o.moments()
+    want = float(np.abs(oracle.divergence(o.prm, om["ux"], om["uy"])).max())
+    say(f"  oracle max|div u| = {want:.6e}, max|u| = {np.hypot(om['ux'], om['uy']).max():.3e}")
+    assert want > 0
+    for prec in (64, 32):
+        g = gpu_sim(wl, phi0, prec, nx=nx, ny=ny, bc_x=bc_x, diag_every=40, kernel_path=kernel_path)
+        ref = gpu_sim(wl, phi0, prec, nx=nx, ny=ny, bc_x=bc_x, kernel_path=kernel_path)
+        g.step(40)
+        ref.step(40)
+        _, d = gpu_moments(g)
+        dn = LbmDiag()
+        rc = g.L.lbm_moments(g.ctx, None, None, None, None, None, None, ctypes.byref(dn))
+        assert rc == 0
+        say(f"  prec {prec}: max|div u| = {d['max_div_u']:.6e} (no planes: {dn.max_div_u:.6e})")
+        assert dn.max_div_u == d["max_div_u"]
+        if prec == 64:
+            assert d["max_div_u"] == pytest.approx(want, rel=1e-9)
+        else:
+            assert abs(d["max_div_u"] - want) <= 1e-8
+        assert g.last_diag()["max_div_u"] == -1.0
+        # the staged velocity did not disturb the state or the next steps
+        g.step(3)
+        ref.step(3)
+        assert all(np.array_equal(a, b) for a, b in zip(gpu_state(g), gpu_state(ref)))
+        g.close()
+        ref.close()
+
+
 def test_nonfinite_detection():
     wl = inputs.ADJOINT
     nx, ny = 64, 32
