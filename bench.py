@@ -3,13 +3,17 @@
 
 Workload: 16384 x 16384 periodic grid, 2000 seeded non-overlapping drops with
 radius ~ U(20, 80), density ratio 100, nu 0.1/0.1, sigma 5e-4, M 0.05, W 4
-(synthetic input; there is no dataset).  One step = the phi/mu stencil pass
-plus the fused collide-and-pull-stream pass, through the C ABI.
+(synthetic input; there is no dataset).  One step = phi, mu, both
+collisions and the pull streaming, in the library's fused step kernel,
+through the C ABI.
 
 Prints one JSON line: FP32 (deviation storage) MLUPS as the value, the FP64
-step beside it, the roofline of the collide-stream kernel measured with HIP
-events on the library's stream, and the CPU oracle timed on a bounded crop
-of the same field.
+step beside it, the roofline of the step kernel measured with HIP events on
+the library's stream, the two-kernel and MRT forms of the FP32 step, the
+4096^2 two-drop coalescence in both precisions, the adjoint/forward cost
+ratio of the 1024^2 (and 2048^2) inverse problem, and the CPU oracle timed
+on a bounded sample of the workload (the same recipe on a periodic 1024^2
+grid), with the FP64 and FP32 GPU errors against it on that sample.
 """
 from __future__ import annotations
 
@@ -149,15 +153,24 @@ def stream_copy_probe(device, nbytes=4 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
-def cpu_baseline(wl, seconds: float):
-    """FP64 oracle (plain loops, OpenMP over rows) on a 1024^2 crop of the field."""
+def cpu_baseline(wl, seconds: float, dev):
+    """FP64 oracle (plain loops, OpenMP over rows) timed on a 1024^2 sample
+    of the workload: the same many-drop recipe on a periodic 1024^2 grid
+    (drops scaled with the area, 8 of them).  A window cut out of the
+    16384^2 field would not do: drops cut at its edges meet across the
+    periodic seam as phi jumps of up to 2 between neighbours, and the run
+    diverges within 50 steps.  The GPU then runs the same field for the
+    same steps in FP64 and FP32, and their phi and velocity errors against
+    the oracle are returned beside the timing."""
     import numpy as np
+    import torch
     import oracle
     from paper_2311_10827_amd import inputs
+    from paper_2311_10827_amd.sim import Sim, make_params
     oracle.build(force=False)
     n = 1024
-    phi = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W,
-                            window=(0, 0, n, n))
+    nd = round(wl.extra["ndrops"] * n * n / (wl.nx * wl.ny))
+    phi = inputs.many_drops(n, nd, wl.extra["rmin"], wl.extra["rmax"], wl.W)
     o = oracle.Sim(oracle.params_for(wl, nx=n, ny=n)).init(phi)
     t = time.perf_counter()
     o.step(2)
@@ -166,13 +179,65 @@ def cpu_baseline(wl, seconds: float):
     t = time.perf_counter()
     o.step(k)
     dt = time.perf_counter() - t
-    return {
+    sample = (f"1024x1024 periodic grid, the many-drop recipe with {nd} drops (the 16384^2 density), "
+              f"{k} FP64 steps, {dt:.1f} s")
+    base = {
         "value": round(n * n * k / dt / 1e6, 3),
         "unit": "MLUPS",
         "cores": oracle.get_threads(),
         "kind": "oracle",
-        "sample": f"1024x1024 crop of the 16384^2 many-drop field (periodic), {k} FP64 steps, {dt:.1f} s",
+        "sample": sample,
     }
+    om = o.moments()
+    del o
+    err = {"sample": f"the same 1024^2 field, {k + 2} steps on the GPU (the step form it takes at that size)",
+           "oracle_max_u": float(np.hypot(om["ux"], om["uy"]).max())}
+    phi_dev = torch.from_numpy(phi).to(dev)
+    for prec in (64, 32):
+        sim = Sim(make_params(wl, precision=prec, nx=n, ny=n), phi_dev, device=dev)
+        sim.step(k + 2)
+        m = sim.moments(diag=False)
+        err[f"fp{prec}"] = {
+            "max_abs_phi": float(np.abs(m["phi"].cpu().numpy() - om["phi"]).max()),
+            "max_abs_u": max(float(np.abs(m["ux"].cpu().numpy() - om["ux"]).max()),
+                             float(np.abs(m["uy"].cpu().numpy() - om["uy"]).max())),
+        }
+        sim.close()
+        del sim, m
+    log(f"[bench] errors against the oracle: {err}")
+    return base, err
+
+
+def coalescence_leg(dev, steps: int, warmup: int):
+    """Two-drop coalescence at 4096^2 (R 400, W 5, seeded noise 1e-3,
+    density ratio 1000, dynamic viscosity ratio 100): ms per step and MLUPS
+    in FP32 and FP64, with HIP events on the library's stream."""
+    import torch
+    from paper_2311_10827_amd import inputs
+    from paper_2311_10827_amd.sim import Sim, make_params
+    wl = inputs.COALESCENCE
+    phi = inputs.two_drops(wl.nx, wl.ny, wl.extra["R"], wl.W, noise=wl.extra["noise"], workload_id=3)
+    phi_dev = torch.from_numpy(phi).to(dev)
+    out = {"workload": f"{wl.name}: {wl.nx}x{wl.ny} periodic, two drops R {wl.extra['R']:g} touching at "
+                       f"the centre, noise 1e-3, density ratio 1000, viscosity ratio 100, sigma 1e-3, "
+                       f"M 0.05, W 5; {steps} timed steps"}
+    for prec in (32, 64):
+        sim = Sim(make_params(wl, precision=prec), phi_dev, device=dev)
+        sim.step(warmup)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(sim.stream)
+        sim.step(steps)
+        e1.record(sim.stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        out[f"fp{prec}"] = {"ms_per_step": round(ms, 5), "mlups": round(wl.nx * wl.ny / (ms * 1e-3) / 1e6, 1)}
+        sim.close()
+        del sim
+    del phi_dev
+    torch.cuda.empty_cache()
+    log(f"[bench] coalescence 4096^2: {out}")
+    return out
 
 
 def adjoint_leg(nsteps: int, K: int, n: int = 0):
@@ -264,6 +329,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-two-kernel", action="store_true")
     ap.add_argument("--no-mrt", action="store_true")
+    ap.add_argument("--no-coalescence", action="store_true")
+    ap.add_argument("--coalescence-steps", type=int, default=1000)
     ap.add_argument("--place-tries", type=int, default=3,
                     help="allocations the state placement probe tries (1: take the first)")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
@@ -327,7 +394,8 @@ def main():
     adj = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K)
     # the same at 2048^2, where the forward state no longer fits in the caches
     adj2 = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K, 2048)
-    cpu = None if args.no_cpu else cpu_baseline(wl, args.cpu_seconds)
+    coal = None if args.no_coalescence else coalescence_leg(dev, args.coalescence_steps, args.warmup)
+    cpu, err = (None, None) if args.no_cpu else cpu_baseline(wl, args.cpu_seconds, dev)
 
     out = {
         "metric": METRIC,
@@ -351,6 +419,7 @@ def main():
         "roofline": r32["roofline"],
         "measured_bytes_frac": r32["measured_bytes_frac"],
         "cpu_baseline": cpu,
+        "error_vs_oracle": err,
         "kernel_ms": round(r32["kernel_ms"], 4),
         "algorithmic_bytes_per_cell": STEP_BYTES[32],
         "stream_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
@@ -376,6 +445,7 @@ def main():
         "adjoint_2048": None if adj2 is None else {
             k: adj2[k] for k in ("workload", "forward_ms_per_step", "forward_reference",
                                  "adjoint_ms_per_step_incl_recompute", "ratio")},
+        "coalescence_4096": coal,
         "diag_after": r32["diag_after"],
     }
     print(json.dumps(out), flush=True)

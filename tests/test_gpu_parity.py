@@ -142,6 +142,7 @@ def test_fp64_well_balanced_fixed_point():
     g.step(1000)
     gm, d = gpu_moments(g)
     assert np.hypot(gm["ux"], gm["uy"]).max() <= 1e-14
+    assert d["max_div_u"] <= 1e-14  # divergence-free to round-off
     assert d["kinetic_energy"] <= 1e-26
     assert np.abs(gm["phi"] - ps).max() <= 1e-12
     assert np.abs(gm["mu"] - mu0).max() <= 1e-15
@@ -178,6 +179,7 @@ def test_fp32_well_balanced_fixed_point():
     g.step(2000)
     gm, d = gpu_moments(g)
     assert np.hypot(gm["ux"], gm["uy"]).max() <= 1e-6
+    assert d["max_div_u"] <= 1e-6
     assert np.abs(gm["phi"] - ps).max() <= 1e-5
 
 

@@ -248,6 +248,7 @@ def test_well_balanced_fixed_point(shape, bcx):
         umax = np.hypot(m["ux"], m["uy"]).max()
         E = 0.5 * (m["rho"] * (m["ux"] ** 2 + m["uy"] ** 2)).sum()
         assert umax <= 1e-14, (n, umax)
+        assert np.abs(oracle.divergence(prm, m["ux"], m["uy"])).max() <= 1e-14
         assert np.abs(m["phi"] - ps).max() <= 1e-12
         assert E <= 1e-26
         assert np.abs(m["mu"] - mu0).max() <= 1e-15
