@@ -223,6 +223,31 @@ def divergence(prm: Params, ux, uy):
     return gxx + gyy
 
 
+BULK_TOL = 0.01  # a bulk cell's phase fraction lies within this of the grid's extreme
+
+
+def laplace_jump(prm: Params, phi, mu, p):
+    """Pressure jump between the two bulk phases, (mean of P^ over bulk-A
+    cells) - (mean over bulk-B cells), with P^ = p + phi mu - psi(phi) and
+    psi(phi) = beta (phi - phi_A)^2 (phi - phi_B)^2 (Sec. 2.1, eqs.
+    bulk_energy, chemical_potencial): at mechanical equilibrium under the
+    force -phi grad mu this is the quantity that jumps by sigma / R across a
+    drop of radius R.  With the phase-A fraction s = (phi - phi_B) /
+    (phi_A - phi_B), a cell is bulk A where s >= max(s) - 0.01 and bulk B
+    where s <= min(s) + 0.01 (relative to the grid's extremes, since the
+    bulk values themselves shift with the curvature).  Returns (jump,
+    number of bulk-A cells, of bulk-B cells); the jump is 0 where either
+    count is 0 or the two sets overlap (no interface)."""
+    phi, mu, p = (np.asarray(a, dtype=np.float64) for a in (phi, mu, p))
+    ph_hat = p + phi * mu - prm.beta * (phi - prm.phi_A) ** 2 * (phi - prm.phi_B) ** 2
+    s = (phi - prm.phi_B) / (prm.phi_A - prm.phi_B)
+    a, b = s >= s.max() - BULK_TOL, s <= s.min() + BULK_TOL
+    na, nb = int(a.sum()), int(b.sum())
+    if na == 0 or nb == 0 or np.any(a & b):
+        return 0.0, na, nb
+    return float(ph_hat[a].mean() - ph_hat[b].mean()), na, nb
+
+
 def laplacian(prm: Params, field):
     field = _f64(field, (prm.ny, prm.nx))
     out = np.zeros_like(field)

@@ -12,6 +12,7 @@ import sys
 import numpy as np
 import pytest
 
+import oracle
 from harness import compare_state, gpu_moments, gpu_sim, gpu_state, oracle_sim
 from paper_2311_10827_amd import inputs
 
@@ -60,6 +61,12 @@ def test_random_configuration(k, path):
     assert d32["n_nonfinite"] == 0
     assert np.abs(m32["phi"] - om["phi"]).max() <= 1e-5
     assert max(np.abs(m32["ux"] - om["ux"]).max(), np.abs(m32["uy"] - om["uy"]).max()) <= 1e-6
+    # max |div u|: the stencil's weights sum to 1 in absolute value per
+    # derivative, so a velocity error e moves it by at most 2 e
+    want = float(np.abs(oracle.divergence(o.prm, om["ux"], om["uy"])).max())
+    _, d64 = gpu_moments(g64)
+    assert abs(d64["max_div_u"] - want) <= 1e-9 * want + 1e-18
+    assert abs(d32["max_div_u"] - want) <= 2e-6
 
 
 N_VARIANT_CASES = 8

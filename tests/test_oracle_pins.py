@@ -408,6 +408,29 @@ def test_laplace_law():
     Reff = np.sqrt(((ph - po) / (pi - po)).sum() / np.pi)
     ratio = (Ph[r < R / 2].mean() - Ph[r > R + 12].mean()) / (sig / Reff)
     assert 0.97 <= ratio <= 1.02, ratio
+    # the diagnostic's bulk-phase definition measures the same jump
+    jump, na, nb = oracle.laplace_jump(prm, ph, m["mu"], m["p"])
+    assert na > 0 and nb > 0
+    assert 0.97 <= jump / (sig / Reff) <= 1.02, jump / (sig / Reff)
+
+
+def test_laplace_jump_flat_interface_and_symmetries():
+    # A flat interface at the discrete equilibrium carries no pressure jump
+    # (no curvature); swapping the phase labels flips the jump's sign and a
+    # constant added to p leaves it unchanged.
+    import dataclasses
+    prm, ps, _ = _wb_state("flat", 1)
+    m = oracle.Sim(prm).init(ps).step(10).moments()
+    jump, na, nb = oracle.laplace_jump(prm, m["phi"], m["mu"], m["p"])
+    assert na > 0 and nb > 0 and abs(jump) <= 1e-6 * inputs.FLAT.sigma
+    prm, ps, _ = _wb_state("drop", 0)
+    m = oracle.Sim(prm).init(ps).step(10).moments()
+    jump, na, nb = oracle.laplace_jump(prm, m["phi"], m["mu"], m["p"])
+    assert jump > 0 and na > 0 and nb > 0
+    swapped = dataclasses.replace(prm, phi_A=prm.phi_B, phi_B=prm.phi_A)
+    assert oracle.laplace_jump(swapped, m["phi"], m["mu"], m["p"]) == (-jump, nb, na)
+    shifted = oracle.laplace_jump(prm, m["phi"], m["mu"], m["p"] + 0.37)[0]
+    assert abs(shifted - jump) <= 1e-12 * abs(jump) + 1e-15
 
 
 @pytest.mark.parametrize("collision", [oracle.BGK, oracle.MRT])
