@@ -169,7 +169,19 @@ typedef struct lbm_diag {
                            * the recovered equations are incompressible.
                            * Formed by lbm_moments only: -1 from
                            * lbm_last_diag */
+  double laplace_dP;      /* mean of P^ = p + phi mu - psi(phi), psi the
+                           * double well of Sec. 2.1 (eq. bulk_energy), over
+                           * the bulk-A cells minus its mean over the bulk-B
+                           * cells: the jump that equals sigma / R across a
+                           * drop at mechanical equilibrium.  With the
+                           * phase-A fraction s = (phi - phi_B) /
+                           * (phi_A - phi_B), bulk A is s >= max(s) - 0.01
+                           * and bulk B s <= min(s) + 0.01.  0 unless both
+                           * sets are non-empty and disjoint.  Formed by
+                           * lbm_moments only */
   int64_t n_nonfinite;    /* cells whose phi, mu, u or p is not finite */
+  int64_t n_bulk_A, n_bulk_B; /* cells in the two bulk sets (0 from
+                               * lbm_last_diag) */
   int64_t step;
 } lbm_diag;
 
@@ -222,11 +234,11 @@ int64_t lbm_step_count(const lbm_ctx* ctx);
 /*
  * Moments of the current pre-collision state: phi, mu, ux, uy, p, rho.
  * Each output is device FP64 [ny][nx] or NULL.  If diag is not NULL it
- * receives the diagnostics (host struct), max_div_u included; that makes
- * the call synchronise the stream.  With diag and a NULL ux or uy, the
- * velocity is staged in the state's idle population buffer (the one the
- * next step overwrites), so no memory beyond the state is needed.  Does
- * not advance time.
+ * receives the diagnostics (host struct), max_div_u and laplace_dP
+ * included; that makes the call synchronise the stream.  With diag, the
+ * fields among phi, mu, ux, uy, p that are NULL are staged in the state's
+ * idle population buffer (the one the next step overwrites), so no memory
+ * beyond the state is needed.  Does not advance time.
  */
 int lbm_moments(lbm_ctx* ctx, double* phi, double* mu, double* ux, double* uy, double* p,
                 double* rho, lbm_diag* diag);

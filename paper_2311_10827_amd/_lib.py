@@ -52,8 +52,9 @@ class LbmDerived(ctypes.Structure):
 class LbmDiag(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("sum_phi", "source_sum", "kinetic_energy", "max_u", "min_rho", "max_rho",
-                 "mu_min", "mu_max", "phi_min", "phi_max", "max_div_u")] + [
-        ("n_nonfinite", ctypes.c_int64), ("step", ctypes.c_int64)]
+                 "mu_min", "mu_max", "phi_min", "phi_max", "max_div_u", "laplace_dP")] + [
+        ("n_nonfinite", ctypes.c_int64), ("n_bulk_A", ctypes.c_int64), ("n_bulk_B", ctypes.c_int64),
+        ("step", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

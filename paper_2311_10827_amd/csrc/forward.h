@@ -714,6 +714,73 @@ __global__ __launch_bounds__(256) void k_max_reduce(const double* __restrict__ p
   if (threadIdx.x == 0) out[0] = m;
 }
 
+// Sums of NV values over the 256 lanes of a block, in a fixed order (wave
+// butterflies, then the four waves in order), written to out[0..NV) by
+// thread 0.
+template <int NV>
+__device__ __forceinline__ void block_sum_write(double (&v)[NV], double* __restrict__ out) {
+  __shared__ double red[4][NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k)
+    for (int s = 32; s >= 1; s >>= 1) v[k] += __shfl_xor(v[k], s, 64);
+  if ((threadIdx.x & 63) == 0)
+    for (int k = 0; k < NV; ++k) red[threadIdx.x >> 6][k] = v[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+    for (int k = 0; k < NV; ++k) out[k] = ((red[0][k] + red[1][k]) + red[2][k]) + red[3][k];
+}
+
+// Laplace pressure jump, first pass.  P^ = p + phi mu - psi(phi), psi(phi) =
+// beta (phi - phi_A)^2 (phi - phi_B)^2 (Sec. 2.1, eqs. bulk_energy,
+// chemical_potencial), in FP64 from dense planes [ny][nx].  With the
+// phase-A fraction s = (phi - phi_B) / (phi_A - phi_B), a cell is bulk A if
+// s >= max(s) - LAP_BULK_TOL and bulk B if s <= min(s) + LAP_BULK_TOL; the
+// extremes come from the grid's phi extrema (ext = {phi_min, phi_max}).
+// Block b takes cells b*256 + t, stepping by the whole grid, and writes
+// (sum of P^ over A, count A, sum over B, count B, count of cells in both)
+// to part[5b..5b+5).
+constexpr double LAP_BULK_TOL = 0.01;
+__global__ __launch_bounds__(256) void k_laplace_part(const KP p, const double* __restrict__ phi,
+                                                       const double* __restrict__ mu,
+                                                       const double* __restrict__ pr,
+                                                       const double* __restrict__ ext,
+                                                       double* __restrict__ part) {
+  const long long n = (long long)p.nx * p.ny;
+  const double d = p.phiA - p.phiB, beta = 0.25 * p.beta4;
+  const double s_lo = (ext[0] - p.phiB) / d, s_hi = (ext[1] - p.phiB) / d;
+  const double a_min = fmax(s_lo, s_hi) - LAP_BULK_TOL, b_max = fmin(s_lo, s_hi) + LAP_BULK_TOL;
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (long long k = (long long)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (long long)gridDim.x * blockDim.x) {
+    const double ph = phi[k];
+    const double s = (ph - p.phiB) / d;
+    const bool a = s >= a_min, b = s <= b_max;
+    if (a || b) {
+      const double dA = ph - p.phiA, dB = ph - p.phiB;
+      const double hat = (pr[k] + ph * mu[k]) - (beta * (dA * dA)) * (dB * dB);
+      if (a) {
+        v[0] += hat;
+        v[1] += 1.0;
+      }
+      if (b) {
+        v[2] += hat;
+        v[3] += 1.0;
+      }
+      if (a && b) v[4] += 1.0;
+    }
+  }
+  block_sum_write<5>(v, part + 5 * (long long)blockIdx.x);
+}
+
+// Second pass: the n partial 5-tuples summed in a fixed order into out[0..5).
+__global__ __launch_bounds__(256) void k_laplace_reduce(const double* __restrict__ part, int n,
+                                                         double* __restrict__ out) {
+  double v[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int k = threadIdx.x; k < n; k += blockDim.x)
+    for (int j = 0; j < 5; ++j) v[j] += part[5 * k + j];
+  block_sum_write<5>(v, out);
+}
+
 __global__ __launch_bounds__(256) void k_reduce_diag(const double* __restrict__ partials, long long n,
                                                       long long chunk, double* __restrict__ out) {
   Diag d;

@@ -44,8 +44,9 @@ struct lbm_ctx {
   bool fused;           // lbm_step runs the fused kernel
   double* partials;
   double* red_mid;      // [RED_BLOCKS][NQ]: first-level reduction results
-  double* diag_dev;     // [2][NQ]: fused step diagnostics, moments diagnostics; then max |div u|
-  double* diag_host;    // pinned [2][NQ] + 1
+  double* diag_dev;     // [2][NQ]: fused step diagnostics, moments diagnostics; then
+                        // max |div u| and the five sums of the Laplace jump
+  double* diag_host;    // pinned [2][NQ] + 6
   int64_t diag_step;
   bool diag_pending, diag_seen, nonfinite;
   hipEvent_t diag_ev;
@@ -156,8 +157,9 @@ Layout layout_of(const lbm_params* p) {
   L.ntx2 = (p->nx + K2_TX - 1) / K2_TX;
   L.nty2 = (p->ny + K2_TY - 1) / K2_TY;
   const size_t nparts = (size_t)L.ntx2 * L.nty2;
-  // partials, first-level reduction, [2][NQ] diagnostics and max |div u|
-  L.ws_bytes = round_up((nparts * NQ + (RED_BLOCKS + 2) * NQ + 1) * sizeof(double), 256);
+  // partials, first-level reduction, [2][NQ] diagnostics, max |div u| and
+  // the five sums of the Laplace jump
+  L.ws_bytes = round_up((nparts * NQ + (RED_BLOCKS + 2) * NQ + 6) * sizeof(double), 256);
   return L;
 }
 
@@ -288,9 +290,10 @@ int launch_reduce(lbm_ctx* c, int slot, long long n) {
   return LBM_OK;
 }
 
-// v: the NQ reduced quantities; max_div_u: max |div u| (lbm_moments) or -1
-// (the fused step's diagnostics, which do not form it).
-void fill_diag(const double* v, int64_t step, lbm_diag* d, double max_div_u) {
+// v: the NQ reduced quantities; x: max |div u| and the five sums of the
+// Laplace jump (lbm_moments), or NULL for the fused step's diagnostics,
+// which form neither (max_div_u = -1, no bulk cells).
+void fill_diag(const double* v, int64_t step, lbm_diag* d, const double* x) {
   d->sum_phi = v[0];
   d->source_sum = v[1];
   d->kinetic_energy = v[2];
@@ -301,7 +304,11 @@ void fill_diag(const double* v, int64_t step, lbm_diag* d, double max_div_u) {
   d->mu_max = v[7];
   d->phi_min = v[8];
   d->phi_max = v[9];
-  d->max_div_u = max_div_u;
+  d->max_div_u = x ? x[0] : -1.0;
+  d->n_bulk_A = x ? (int64_t)x[2] : 0;
+  d->n_bulk_B = x ? (int64_t)x[4] : 0;
+  // both bulk sets non-empty and disjoint (an interface between them)
+  d->laplace_dP = x && x[2] > 0 && x[4] > 0 && x[5] == 0 ? x[1] / x[2] - x[3] / x[4] : 0.0;
   d->n_nonfinite = (int64_t)v[10];
   d->step = step;
 }
@@ -398,15 +405,18 @@ template <typename T>
 int moments_impl(lbm_ctx* c, MomOut mo, lbm_diag* diag) {
   int r = launch_phi_mu<T>(c);
   if (r) return r;
-  // max |div u| needs the velocity of every cell.  Where the caller asks
-  // for diagnostics without the velocity planes, the moments kernel writes
-  // them into the population buffer the next step overwrites entirely (it
-  // holds 18 or 19 planes; two dense FP64 planes fit).
+  // max |div u| and the Laplace jump need u, phi, mu and p of every cell.
+  // Where the caller asks for diagnostics without those planes, the moments
+  // kernel writes them into the population buffer the next step overwrites
+  // entirely (it holds 18 or 19 planes; five dense FP64 planes fit).
   const long long n = (long long)c->p.nx * c->p.ny;
   if (diag) {
     double* scratch = reinterpret_cast<double*>(popbuf<T>(c, c->cur ^ 1));
     if (!mo.ux) mo.ux = scratch;
     if (!mo.uy) mo.uy = scratch + n;
+    if (!mo.phi) mo.phi = scratch + 2 * n;
+    if (!mo.mu) mo.mu = scratch + 3 * n;
+    if (!mo.p) mo.p = scratch + 4 * n;
   }
   r = launch_collide<T, M_MOMENTS>(c, mo);
   if (r) return r;
@@ -420,10 +430,17 @@ int moments_impl(lbm_ctx* c, MomOut mo, lbm_diag* diag) {
     hipLaunchKernelGGL(k_max_reduce, dim3(1), dim3(256), 0, c->stream, c->red_mid, RED_BLOCKS,
                        c->diag_dev + 2 * NQ);
     LAUNCHCHK(c);
-    HIPCHK(c, hipMemcpyAsync(c->diag_host + NQ, c->diag_dev + NQ, (NQ + 1) * sizeof(double),
+    // the phi extrema of the moments diagnostics set the bulk thresholds
+    hipLaunchKernelGGL(k_laplace_part, dim3(RED_BLOCKS), dim3(256), 0, c->stream, c->kp, mo.phi, mo.mu,
+                       mo.p, c->diag_dev + NQ + 8, c->red_mid);
+    LAUNCHCHK(c);
+    hipLaunchKernelGGL(k_laplace_reduce, dim3(1), dim3(256), 0, c->stream, c->red_mid, RED_BLOCKS,
+                       c->diag_dev + 2 * NQ + 1);
+    LAUNCHCHK(c);
+    HIPCHK(c, hipMemcpyAsync(c->diag_host + NQ, c->diag_dev + NQ, (NQ + 6) * sizeof(double),
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    fill_diag(c->diag_host + NQ, c->step, diag, c->diag_host[2 * NQ]);
+    fill_diag(c->diag_host + NQ, c->step, diag, c->diag_host + 2 * NQ);
   }
   return LBM_OK;
 }
@@ -675,7 +692,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   // the 16-bit low word of f_0 pays where the step is bound by HBM; on
   // smaller states its arithmetic costs more than the bytes it saves
   c->lo16 = p->precision == 32 && L.state_bytes > LO16_STATE_BYTES;
-  hipError_t e = hipHostMalloc((void**)&c->diag_host, (2 * NQ + 1) * sizeof(double), hipHostMallocDefault);
+  hipError_t e = hipHostMalloc((void**)&c->diag_host, (2 * NQ + 6) * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
     return LBM_EHIP;
@@ -722,7 +739,7 @@ int lbm_last_diag(lbm_ctx* c, lbm_diag* diag) {
   int r = consume_diag(c, true);
   if (r) return r;
   if (!c->diag_seen) return LBM_ESTATE;
-  fill_diag(c->diag_host, c->diag_step, diag, -1.0);
+  fill_diag(c->diag_host, c->diag_step, diag, nullptr);
   return diag_bad(c->diag_host) ? LBM_ENONFINITE : LBM_OK;
 }
 

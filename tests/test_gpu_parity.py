@@ -144,6 +144,11 @@ def test_fp64_well_balanced_fixed_point():
     assert np.hypot(gm["ux"], gm["uy"]).max() <= 1e-14
     assert d["max_div_u"] <= 1e-14  # divergence-free to round-off
     assert d["kinetic_energy"] <= 1e-26
+    # the Laplace jump of the fixed point, as the oracle measures it
+    om = oracle.Sim(prm).init(ps).step(1000).moments()
+    jump, na, nb = oracle.laplace_jump(prm, om["phi"], om["mu"], om["p"])
+    assert (d["n_bulk_A"], d["n_bulk_B"]) == (na, nb)
+    assert d["laplace_dP"] == pytest.approx(jump, rel=1e-9)
     assert np.abs(gm["phi"] - ps).max() <= 1e-12
     assert np.abs(gm["mu"] - mu0).max() <= 1e-15
 
@@ -298,6 +303,9 @@ def test_max_div_u_matches_oracle(bc_x, kernel_path):
     want = float(np.abs(oracle.divergence(o.prm, om["ux"], om["uy"])).max())
     say(f"  oracle max|div u| = {want:.6e}, max|u| = {np.hypot(om['ux'], om['uy']).max():.3e}")
     assert want > 0
+    jump, na, nb = oracle.laplace_jump(o.prm, om["phi"], om["mu"], om["p"])
+    say(f"  oracle Laplace jump {jump:.6e} over {na} bulk-A and {nb} bulk-B cells")
+    assert na > 0 and nb > 0
     for prec in (64, 32):
         g = gpu_sim(wl, phi0, prec, nx=nx, ny=ny, bc_x=bc_x, diag_every=40, kernel_path=kernel_path)
         ref = gpu_sim(wl, phi0, prec, nx=nx, ny=ny, bc_x=bc_x, kernel_path=kernel_path)
@@ -307,13 +315,22 @@ def test_max_div_u_matches_oracle(bc_x, kernel_path):
         dn = LbmDiag()
         rc = g.L.lbm_moments(g.ctx, None, None, None, None, None, None, ctypes.byref(dn))
         assert rc == 0
-        say(f"  prec {prec}: max|div u| = {d['max_div_u']:.6e} (no planes: {dn.max_div_u:.6e})")
-        assert dn.max_div_u == d["max_div_u"]
+        say(f"  prec {prec}: max|div u| = {d['max_div_u']:.6e} (no planes: {dn.max_div_u:.6e}), "
+            f"Laplace jump {d['laplace_dP']:.6e} ({d['n_bulk_A']}, {d['n_bulk_B']} cells)")
+        assert dn.max_div_u == d["max_div_u"] and dn.laplace_dP == d["laplace_dP"]
+        assert (dn.n_bulk_A, dn.n_bulk_B) == (d["n_bulk_A"], d["n_bulk_B"])
         if prec == 64:
             assert d["max_div_u"] == pytest.approx(want, rel=1e-9)
+            # the bulk sets are decided in FP64 from phi on both sides
+            assert (d["n_bulk_A"], d["n_bulk_B"]) == (na, nb)
+            assert d["laplace_dP"] == pytest.approx(jump, rel=1e-9)
         else:
             assert abs(d["max_div_u"] - want) <= 1e-8
-        assert g.last_diag()["max_div_u"] == -1.0
+            # FP32 phi may move a threshold cell between the sets
+            assert abs(d["n_bulk_A"] - na) <= 0.01 * na and abs(d["n_bulk_B"] - nb) <= 0.01 * nb
+            assert abs(d["laplace_dP"] - jump) <= 1e-2 * abs(jump)
+        ld = g.last_diag()
+        assert ld["max_div_u"] == -1.0 and ld["laplace_dP"] == 0.0 and ld["n_bulk_A"] == 0
         # the staged velocity did not disturb the state or the next steps
         g.step(3)
         ref.step(3)
