@@ -354,6 +354,16 @@ def main():
 
     wl = inputs.THROUGHPUT
     dev = torch.device("cuda:0")
+    # The adjoint legs run first, on a fresh heap: after the 16384^2 legs
+    # have taken and released about 130 GB, their snapshots land on other
+    # pages and the adjoint step measures 2-3 % slower.
+    adj = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K)
+    # the same at 2048^2, where the forward state no longer fits in the caches
+    adj2 = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K, 2048)
+    import gc
+    gc.collect()
+    torch.cuda.empty_cache()
+    log(f"[bench] after the adjoint legs: {torch.cuda.memory_allocated() / 2**30:.2f} GiB still allocated")
     log("[bench] generating the 16384^2 many-drop field")
     phi0 = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
     phi0_dev = torch.from_numpy(phi0).to(dev)
@@ -391,9 +401,6 @@ def main():
     del phi0_dev
     torch.cuda.empty_cache()
     copy_gbps = None if args.no_copy else stream_copy_probe(dev)
-    adj = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K)
-    # the same at 2048^2, where the forward state no longer fits in the caches
-    adj2 = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K, 2048)
     coal = None if args.no_coalescence else coalescence_leg(dev, args.coalescence_steps, args.warmup)
     cpu, err = (None, None) if args.no_cpu else cpu_baseline(wl, args.cpu_seconds, dev)
 
