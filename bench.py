@@ -354,9 +354,7 @@ def main():
 
     wl = inputs.THROUGHPUT
     dev = torch.device("cuda:0")
-    # The adjoint legs run first, on a fresh heap: after the 16384^2 legs
-    # have taken and released about 130 GB, their snapshots land on other
-    # pages and the adjoint step measures 2-3 % slower.
+    # the adjoint legs first, while the heap is fresh
     adj = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K)
     # the same at 2048^2, where the forward state no longer fits in the caches
     adj2 = None if args.no_adjoint else adjoint_leg(args.adjoint_steps, args.adjoint_K, 2048)
