@@ -81,6 +81,10 @@ def load() -> ctypes.CDLL:
         raise ImportError(
             f"{LIB_PATH} is missing: build it with `python -m paper_2311_10827_amd.build` "
             "(there is no CPU fallback)")
+    # torch ships its own HIP runtime; loaded first, it is the one the
+    # library binds to, so both share one runtime (the library loaded before
+    # torch made lbm_init fail with a HIP error on MI355X).
+    import torch  # noqa: F401
     L = ctypes.CDLL(LIB_PATH)
     vp, i32, i64, dp = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_void_p
     P = ctypes.POINTER(LbmParams)
