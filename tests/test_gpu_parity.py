@@ -358,28 +358,46 @@ def test_nonfinite_detection():
     assert g.last_diag()["ok"] is False
 
 
+def _full_size_case(name):
+    """Full-size workload, its initial field and the centres of the sampled
+    windows: corners (periodic wrap), points on interfaces, random points."""
+    rng = np.random.default_rng(77)
+    if name == "many_drops_16384":
+        wl = inputs.THROUGHPUT
+        phi0 = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
+        xs, ys, rs = inputs.drop_centres(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
+        pts = [(int(xs[k] + rs[k]) % wl.nx, int(ys[k]) % wl.ny) for k in range(3)]
+    else:
+        wl = inputs.COALESCENCE
+        R = wl.extra["R"]
+        phi0 = inputs.two_drops(wl.nx, wl.ny, R, wl.W, noise=wl.extra["noise"], workload_id=3)
+        c = wl.nx // 2
+        # the contact point between the drops, and the outer and top edges
+        pts = [(c, c), (int(c - (R + wl.W / 2) - R), c), (int(c + (R + wl.W / 2)), int(c + R))]
+    n = wl.nx
+    pts = [(0, 0), (n - 1, n - 1), (n - 4, 5)] + pts + [tuple(rng.integers(0, n, 2)) for _ in range(5)]
+    return wl, phi0, pts
+
+
 @pytest.mark.parametrize("prec", [64, 32])
-def test_full_size_sampled(prec):
-    # 16384^2 many-drop workload in the launch configuration the benchmark
-    # times: one and two steps, checked on sampled windows against the oracle
-    # run on each window (periodic patch, margin 3 cells per step).
-    wl = inputs.THROUGHPUT
-    say(f"[gpu] full size 16384^2 prec={prec}: generating input")
-    phi0 = inputs.many_drops(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
+@pytest.mark.parametrize("name", ["many_drops_16384", "coalescence_4096"])
+def test_full_size_sampled(name, prec):
+    # A full-size workload in the launch configuration the benchmark times:
+    # one and two steps, checked on sampled windows against the oracle run
+    # on each window (periodic patch, margin 3 cells per step).
+    say(f"[gpu] full size {name} prec={prec}: generating input")
+    wl, phi0, pts = _full_size_case(name)
     g = gpu_sim(wl, phi0, prec)
     del phi0
-    rng = np.random.default_rng(77)
-    xs, ys, rs = inputs.drop_centres(wl.nx, wl.extra["ndrops"], wl.extra["rmin"], wl.extra["rmax"], wl.W)
-    # corners (periodic wrap), points on three drop interfaces, random points
-    pts = [(0, 0), (16383, 16383), (16380, 5)]
-    pts += [(int(xs[k] + rs[k]) % 16384, int(ys[k]) % 16384) for k in range(3)]
-    pts += [tuple(rng.integers(0, 16384, 2)) for _ in range(5)]
     H = 10
-    wins = [((x - H) % 16384, (y - H) % 16384, 2 * H, 2 * H) for x, y in pts]
+    wins = [((x - H) % wl.nx, (y - H) % wl.ny, 2 * H, 2 * H) for x, y in pts]
     before = [gpu_state(g, w) for w in wins]
     # FP32: the GPU computes in FP32 from the same (exactly representable)
     # stored state the FP64 oracle starts from; differences are rounding.
-    tol = TOL64 if prec == 64 else 2e-5
+    # The coalescence field carries 1e-3 of noise on |phi| = 1, which phi in
+    # FP32 resolves to 2^-24 (6e-8), i.e. to 6e-5 of itself; mu, F, u and
+    # S = u.grad(phi) inherit that relative error where the noise drives them.
+    tol = TOL64 if prec == 64 else (2e-5 if name == "many_drops_16384" else 1e-4)
     # FP32 differences are rounding of quantities of the size each field has
     # where it is active, so they are scaled by the field's largest magnitude
     # over all sampled windows (bulk windows alone hold FP64 rounding residue).
@@ -395,9 +413,12 @@ def test_full_size_sampled(prec):
         floors = [max(np.abs(st[k][c]).max() for st in ref) for k in range(3)]
         for w, ost in zip(wins, ref):
             gst = gpu_state(g, w)
-            for a, b, fl in zip(gst, ost, floors):
+            for k, (a, b, fl) in enumerate(zip(gst, ost, floors)):
                 scale = max(np.abs(b[c]).max(), 1e-30 if prec == 64 else fl)
-                assert np.abs(a[c] - b[c]).max() <= tol * scale, (prec, nsteps, w)
+                err = np.abs(a[c] - b[c])
+                where = np.unravel_index(int(err.argmax()), err.shape)
+                assert err.max() <= tol * scale, (prec, nsteps, w, ("f", "g", "Sp")[k], float(err.max()),
+                                                  float(scale), where, float(b[c][where]))
 
 
 @pytest.mark.parametrize("prec", [64, 32])
