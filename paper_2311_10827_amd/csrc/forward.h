@@ -507,7 +507,7 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
                                                              T* Spout, T* __restrict__ dphi_out,
                                                              T* __restrict__ mu_out,
                                                              double* __restrict__ partials, int ntx,
-                                                             int H) {
+                                                             int H, int xcd_order) {
   constexpr bool DIAG = MODE == M_STEP_DIAG;
   constexpr int W = Strip<T>::W;
   constexpr int FR = Strip<T>::FR;
@@ -516,7 +516,9 @@ __global__ __launch_bounds__(Strip<T>::W) void k_step_fused(const KP p, const T*
   __shared__ T phr[5][W + 4];     // phi - phi_ref, column x0 - 2 + k
   __shared__ T mur[3][W + 2];     // mu, column x0 - 1 + k
   __shared__ T fr[FR][NF][W];     // gathered f of the strip's own columns
-  const int blk = xcd_tile(blockIdx.x, gridDim.x);
+  // strip order: XCD-contiguous bands, or the dispatch order itself (the
+  // hardware deals consecutive workgroups to the eight XCDs in turn)
+  const int blk = xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int x0 = (blk % ntx) * W, y0 = (blk / ntx) * H;
   const int y1 = y0 + H < p.ny ? y0 + H : p.ny;
   const int t = threadIdx.x;
