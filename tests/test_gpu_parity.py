@@ -132,6 +132,30 @@ def test_fp32_coalescence_crop(path, crop_oracle_1000):
     assert e_phi <= 1e-5 and e_u <= 1e-6
 
 
+def test_coalescence_crop_10000_steps():
+    # the workload's full 10000 steps on the 512^2 crop, in the step form
+    # the library picks at that size: FP64 to 1e-12 relative, FP32 within
+    # 1e-5 in phi and 1e-6 in u of the FP64 oracle
+    wl, phi0, over = _crop()
+    say("[gpu] coalescence crop, 10000 steps: oracle (about a minute on the host)")
+    o = oracle_sim(wl, phi0, **over).step(10000)
+    ostate, om = o.get_state(), o.moments()
+    for prec in (64, 32):
+        g = gpu_sim(wl, phi0, prec, **over)
+        g.step(10000)
+        gm, d = gpu_moments(g)
+        assert d["n_nonfinite"] == 0
+        e_phi = np.abs(gm["phi"] - om["phi"]).max()
+        e_u = max(np.abs(gm["ux"] - om["ux"]).max(), np.abs(gm["uy"] - om["uy"]).max())
+        say(f"  fp{prec}: phi err {e_phi:.3e}  u err {e_u:.3e}  max|u| {np.hypot(om['ux'], om['uy']).max():.3e}")
+        if prec == 64:
+            compare_state(gpu_state(g), ostate, TOL64)
+            compare_moments(gm, om, TOL64)
+        else:
+            assert e_phi <= 1e-5 and e_u <= 1e-6
+        g.close()
+
+
 def test_fp64_well_balanced_fixed_point():
     wl = inputs.DROPLET
     phi0 = inputs.droplet(48, 48, 12.0, 4.0, 23.6, 24.3)
