@@ -153,6 +153,17 @@ def stream_copy_probe(device, nbytes=4 << 30, reps=10):
     return 2 * nbytes / (ms * 1e-3) / 1e9
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(wl, seconds: float, dev):
     """FP64 oracle (plain loops, OpenMP over rows) timed on a 1024^2 sample
     of the workload: the same many-drop recipe on a periodic 1024^2 grid
@@ -190,6 +201,21 @@ def cpu_baseline(wl, seconds: float, dev):
     }
     om = o.moments()
     del o
+    # the same oracle on one thread, a few steps of the same field
+    threads = oracle.get_threads()
+    oracle.set_threads(1)
+    o1 = oracle.Sim(oracle.params_for(wl, nx=n, ny=n)).init(phi)
+    t = time.perf_counter()
+    o1.step(2)
+    k1 = max(2, int(min(seconds / 3, 5.0) / max(time.perf_counter() - t, 1e-6) * 2))
+    t = time.perf_counter()
+    o1.step(k1)
+    dt1 = time.perf_counter() - t
+    del o1
+    oracle.set_threads(threads)
+    base["single_thread"] = {"value": round(n * n * k1 / dt1 / 1e6, 3), "unit": "MLUPS", "steps": k1,
+                             "seconds": round(dt1, 2)}
+    base["cpu_model"] = cpu_model()
     err = {"sample": f"the same 1024^2 field, {k + 2} steps on the GPU (the step form it takes at that size)",
            "oracle_max_u": float(np.hypot(om["ux"], om["uy"]).max())}
     phi_dev = torch.from_numpy(phi).to(dev)
