@@ -363,6 +363,27 @@ def test_max_div_u_matches_oracle(bc_x, kernel_path):
         ref.close()
 
 
+@pytest.mark.parametrize("shape", [(1, 1), (17, 9)])
+def test_moment_diagnostics_without_interface(shape):
+    # a uniform bulk phase: both bulk sets are every cell, so there is no
+    # Laplace jump (0, as the oracle's definition gives), and a fluid at rest
+    # has no divergence
+    nx, ny = shape
+    wl = inputs.ADJOINT
+    phi0 = np.full((ny, nx), 1.0)
+    say(f"[gpu] diagnostics without an interface {nx}x{ny}")
+    o = oracle_sim(wl, phi0, nx=nx, ny=ny).step(5)
+    om = o.moments()
+    want = oracle.laplace_jump(o.prm, om["phi"], om["mu"], om["p"])
+    assert want == (0.0, nx * ny, nx * ny)
+    for prec in (64, 32):
+        g = gpu_sim(wl, phi0, prec, nx=nx, ny=ny).step(5)
+        _, d = gpu_moments(g)
+        assert (d["laplace_dP"], d["n_bulk_A"], d["n_bulk_B"]) == want
+        assert d["max_div_u"] == 0.0 and d["n_nonfinite"] == 0
+        g.close()
+
+
 def test_nonfinite_detection():
     wl = inputs.ADJOINT
     nx, ny = 64, 32
