@@ -29,15 +29,20 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS & % HBM roofline, FP32 vs FP64 step; adjoint/forward step cost ratio"
 HBM_PEAK_GBPS = 8000.0
-# Algorithmic HBM bytes per lattice update (per cell) of the fused step
-# kernel, the only kernel of a step: every population plane read once and
-# written once (18 in FP64; in FP32 18 words plus the 2-byte low word of the
-# rest population of f), the previous-step source read and the new one
-# written.  phi and mu stay on chip.
-STEP_BYTES = {32: 2 * (18 * 4 + 2 + 4), 64: (18 + 18 + 1 + 1) * 8}
-# The two-kernel path also writes phi and mu and reads them back, and reads
-# the f planes twice: +(2 + 2) * 4 + 9 * 4 + 2 B in FP32, +(2 + 2 + 9) * 8 B in FP64.
-TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (2 + 2 + 9) * 4 + 2, 64: STEP_BYTES[64] + (2 + 2 + 9) * 8}
+# Algorithmic HBM bytes per lattice update (per cell) of one step: the
+# method's state, 18 populations and the previous-step source, each read once
+# and written once (152 B in FP32, 304 B in FP64).  The roofline fraction is
+# taken on these.
+STEP_BYTES = {32: 2 * 19 * 4, 64: 2 * 19 * 8}
+# What the fused step kernel itself moves: in FP32 also the 16-bit low word
+# of the rest population of f (read and written) that keeps f_0 to about
+# 2^-40; phi and mu stay on chip.
+STEP_IMPL_BYTES = {32: 2 * (18 * 4 + 2 + 4), 64: STEP_BYTES[64]}
+# The two-kernel design: the phi/mu pass also reads the 9 f planes and writes
+# phi and mu, and the collide pass reads them back: +(9 + 2 + 2) planes.
+TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (9 + 2 + 2) * 4, 64: STEP_BYTES[64] + (9 + 2 + 2) * 8}
+# ... and with the low word of f_0 (read twice, written once) in FP32
+TWO_KERNEL_IMPL_BYTES = {32: STEP_IMPL_BYTES[32] + (9 + 2 + 2) * 4 + 2, 64: TWO_KERNEL_BYTES[64]}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_step_fused_many_drops_16384.json")
 
 
@@ -111,6 +116,7 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
     torch.cuda.empty_cache()
     avg = kms / n
     alg = STEP_BYTES[prec] if kernel_path == 2 else TWO_KERNEL_BYTES[prec]
+    impl = STEP_IMPL_BYTES[prec] if kernel_path == 2 else TWO_KERNEL_IMPL_BYTES[prec]
     ach = alg * ncell / (avg * 1e-3) / 1e9
     traffic = None if mrt else measured_traffic(str(prec) if kernel_path == 2 else f"two_kernel_{prec}")
     return {
@@ -118,6 +124,9 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
         "ms_per_step": ms / steps,
         "wall_s": wall,
         "kernel_ms": avg,
+        "algorithmic_bytes_per_cell": alg,
+        "implementation_bytes_per_cell": impl,
+        "implementation_GBps": round(impl * ncell / (avg * 1e-3) / 1e9, 1),
         "roofline": {
             "bound": "hbm",
             "achieved": round(ach, 1),
@@ -132,6 +141,16 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
         else round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "diag_after": {k: d[k] for k in ("sum_phi", "max_u", "min_rho", "n_nonfinite", "step")},
     }
+
+
+def placement_median(times, alg_bytes, ncell):
+    """The median of the placement probe's per-step times (every allocation it
+    tried) and the roofline fraction on algorithmic bytes at that median, to
+    stand beside the kept (fastest) allocation's."""
+    import statistics
+    med = statistics.median(times)
+    return {"ms_per_step": round(med, 4),
+            "frac": round(alg_bytes * ncell / (med * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4)}
 
 
 def stream_copy_probe(device, nbytes=4 << 30, reps=10):
@@ -452,22 +471,29 @@ def main():
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
         "kernel_ms": round(r32["kernel_ms"], 4),
-        "algorithmic_bytes_per_cell": STEP_BYTES[32],
+        "algorithmic_bytes_per_cell": r32["algorithmic_bytes_per_cell"],
+        "implementation_bytes_per_cell": r32["implementation_bytes_per_cell"],
+        "implementation_GBps": r32["implementation_GBps"],
         "stream_copy_GBps": None if copy_gbps is None else round(copy_gbps, 1),
         "placement_probe_ms_per_step": {k: [round(t, 4) for t in v] for k, v in probe.items()},
+        "placement_probe_median": {k: placement_median(v, STEP_BYTES[int(k[2:])], wl.nx * wl.ny)
+                                   for k, v in probe.items()},
         "fp64": None if r64 is None else {
             "value": round(r64["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r64["ms_per_step"], 4),
-            "kernel_ms": round(r64["kernel_ms"], 4), "algorithmic_bytes_per_cell": STEP_BYTES[64],
+            "kernel_ms": round(r64["kernel_ms"], 4),
+            "algorithmic_bytes_per_cell": r64["algorithmic_bytes_per_cell"],
             "roofline": r64["roofline"], "measured_bytes_frac": r64["measured_bytes_frac"],
         },
         "two_kernel_fp32": None if r2k is None else {
             "value": round(r2k["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r2k["ms_per_step"], 4),
-            "algorithmic_bytes_per_cell": TWO_KERNEL_BYTES[32], "roofline": r2k["roofline"],
+            "algorithmic_bytes_per_cell": r2k["algorithmic_bytes_per_cell"],
+            "implementation_bytes_per_cell": r2k["implementation_bytes_per_cell"], "roofline": r2k["roofline"],
             "measured_bytes_frac": r2k["measured_bytes_frac"],
         },
         "mrt_fp32": None if rmrt is None else {
             "value": round(rmrt["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(rmrt["ms_per_step"], 4),
-            "kernel_ms": round(rmrt["kernel_ms"], 4), "algorithmic_bytes_per_cell": STEP_BYTES[32],
+            "kernel_ms": round(rmrt["kernel_ms"], 4),
+            "algorithmic_bytes_per_cell": rmrt["algorithmic_bytes_per_cell"],
             "roofline": rmrt["roofline"], "rates": {"f": MRT_LEG["mrt_f"], "g": MRT_LEG["mrt_g"]},
         },
         "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),

@@ -58,6 +58,9 @@ enum { LBM_NU_LINEAR = 0, LBM_NU_INVERSE = 1, LBM_NU_EXP = 2 };
 /* Collision operator (lbm_params.collision). */
 enum { LBM_BGK = 0, LBM_MRT = 1 };
 
+/* Storage of the FP32 rest population's low word (lbm_params.lo_format). */
+enum { LBM_LO_AUTO = 0, LBM_LO_16 = 1, LBM_LO_32 = 2 };
+
 /*
  * Problem parameters, in the paper's notation.
  *   phi_A, phi_B   order parameter of the two bulk phases (Sec. 2.1, eq. bulk_energy).
@@ -71,6 +74,13 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
  *                  (eqs. beta, suiface_tension).
  *   M, alpha       mobility and the equilibrium's free parameter;
  *                  tau_f = 1/2 + M / (c_s^2 alpha) (Sec. 2.3.1, eq. mobility).
+ *   use_tau        0: the relaxation times follow from M, alpha, nu_A, nu_B as
+ *                  above.  1: tau_f, tau_gA, tau_gB are given instead and
+ *                  alpha = M / (c_s^2 (tau_f - 1/2)) (eq. mobility solved for
+ *                  alpha) and nu_A,B = c_s^2 (tau_gA,B - 1/2) (Sec. 2.3.2)
+ *                  are derived from them; the alpha, nu_A, nu_B fields are
+ *                  then ignored.  Each tau must exceed 1/2.
+ *   tau_f, tau_gA, tau_gB   the relaxation times, read only with use_tau = 1.
  *   gx, gy         body force G added to the interfacial force (Sec. 2.3.2).
  *   bc_x, bc_y     LBM_PERIODIC, or LBM_WALL: half-way bounce-back for both
  *                  populations, and phi, mu mirrored across the wall in the
@@ -78,9 +88,9 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
  *   precision      64: populations stored and updated in FP64.
  *                  32: populations stored and updated in FP32; the rest
  *                      population of f, of order one, is held as an
- *                      unevaluated pair hi + lo (FP32 words; for states
- *                      above 1 GiB lo is a 16-bit fraction of ulp(hi), about
- *                      2^-40 relative) offset by (phi_A + phi_B) / 2, the
+ *                      unevaluated pair hi + lo (hi an FP32 word, lo an
+ *                      FP32 word or a 16-bit fraction of ulp(hi), about
+ *                      2^-40 relative: lo_format) offset by (phi_A + phi_B) / 2, the
  *                      others are small deviations
  *                      from the rest equilibrium; diagnostics stay FP64.
  *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
@@ -118,6 +128,13 @@ enum { LBM_BGK = 0, LBM_MRT = 1 };
  *                  sum_{i!=0} g_i = (8 rho + e - eps)/9.  Every rate must lie
  *                  in (0, 2); with all rates equal to the BGK ones the result
  *                  is the BGK step.
+ *   lo_format      FP32 only (ignored for precision 64): the storage of the
+ *                  low word lo of the rest population's pair hi + lo.
+ *                  LBM_LO_AUTO: 16 bits for states above 1 GiB (where the
+ *                  step is bound by HBM traffic), an FP32 word below;
+ *                  LBM_LO_16: always the 16-bit fraction of ulp(hi);
+ *                  LBM_LO_32: always an FP32 word.  The state size does not
+ *                  depend on it.
  */
 typedef struct lbm_params {
   int32_t nx, ny;
@@ -137,15 +154,20 @@ typedef struct lbm_params {
   int32_t collision;
   double mrt_f[4];
   double mrt_g[2];
+  int32_t lo_format;
+  int32_t use_tau;
+  double tau_f, tau_gA, tau_gB;
 } lbm_params;
 
 /* Derived constants (lattice units). */
 typedef struct lbm_derived {
   double kappa, beta;     /* as used by the step */
   double sigma, W;        /* surface tension and width implied by kappa, beta */
-  double tau_f;           /* 1/2 + M / (c_s^2 alpha) */
-  double tau_gA, tau_gB;  /* 1/2 + nu_A / c_s^2, 1/2 + nu_B / c_s^2 */
-  double alpha;
+  double tau_f;           /* 1/2 + M / (c_s^2 alpha), or as given (use_tau) */
+  double tau_gA, tau_gB;  /* 1/2 + nu_A / c_s^2, 1/2 + nu_B / c_s^2, or as given */
+  double alpha;           /* as given, or M / (c_s^2 (tau_f - 1/2)) (use_tau) */
+  double nu_A, nu_B;      /* as given, or c_s^2 (tau_g - 1/2) (use_tau) */
+  int32_t lo16;           /* 1 if an FP32 state keeps the low word in 16 bits */
 } lbm_derived;
 
 /*
@@ -192,7 +214,8 @@ typedef struct lbm_ctx lbm_ctx;
  * rho_A, rho_B <= 0; nu_A, nu_B <= 0; M <= 0; alpha <= 0; kappa or beta
  * < 0 (or sigma, W <= 0 with use_sigma_W); diag_every < 0; kernel_path not
  * 0..2; nu_form not one of LBM_NU_*; collision not LBM_BGK or LBM_MRT; with
- * LBM_MRT, an MRT rate outside (0, 2). */
+ * LBM_MRT, an MRT rate outside (0, 2); lo_format not one of LBM_LO_*;
+ * use_tau not 0/1; with use_tau, a relaxation time <= 1/2 or not finite. */
 int lbm_derive(const lbm_params* p, lbm_derived* out);
 
 /* Bytes the caller must allocate for the state and the workspace (0 if `p`
@@ -232,7 +255,13 @@ int lbm_step(lbm_ctx* ctx, int64_t n);
 int64_t lbm_step_count(const lbm_ctx* ctx);
 
 /*
- * Moments of the current pre-collision state: phi, mu, ux, uy, p, rho.
+ * Moments of the current pre-collision state: phi = sum_i f_i (Sec. 2.3.1,
+ * eq. order-parameter); mu (Sec. 2.1, eq. chemical_potencial, with the
+ * isotropic Laplacian of Sec. 2.3.2, eq. Laplace); u from
+ * rho u = sum_i c_i g_i + F/2 and p from the non-rest g, u.grad(rho)/2 and
+ * rho s_0(u) (Sec. 2.3.2, the macroscopic subequations, with
+ * F = -phi grad(mu) + G and the isotropic gradients of eq. gradient); rho
+ * linear in phi (Sec. 2.3.2, before eq. vis).
  * Each output is device FP64 [ny][nx] or NULL.  If diag is not NULL it
  * receives the diagnostics (host struct), max_div_u and laplace_dP
  * included; that makes the call synchronise the stream.  With diag, the
@@ -310,10 +339,11 @@ int lbm_step_into(lbm_ctx* ctx, void* src, void* dst);
  * same operator).
  *
  * Parameter gradients accumulate in the adjoint workspace for
- * theta = (kappa, beta, alpha, tau_f, nu_A, nu_B), each taken as independent
- * (tau_f = 1/2 + M/(c_s^2 alpha) and tau_g = 1/2 + nu/c_s^2 relate them to
- * M and the relaxation times).  The MRT rates mrt_f, mrt_g are constants,
- * not differentiated.
+ * theta = (kappa, beta, alpha, tau_f, nu_A, nu_B), each taken as independent;
+ * lbm_adjoint_theta returns them in that basis or in the basis
+ * (kappa, beta, M, tau_f, tau_gA, tau_gB) of the mobility and the
+ * relaxation times.  The MRT rates mrt_f, mrt_g are constants, not
+ * differentiated.
  * ---------------------------------------------------------------------- */
 
 /* Bytes of the adjoint workspace (7 planes plus parameter partials). */
@@ -340,9 +370,15 @@ int lbm_adjoint_segment(lbm_ctx* ctx, void* const* snaps, int L, void* lam, void
  * scratch: a device buffer of the adjoint's size, distinct from lam0. */
 int lbm_adjoint_init(lbm_ctx* ctx, const void* state, const double* phi0, const void* lam0,
                      void* scratch, double* dphi0);
-/* Copy the accumulated dL/dtheta to out[6] (host; synchronises) and, if
- * reset != 0, zero it. */
-int lbm_adjoint_theta(lbm_ctx* ctx, double* out, int reset);
+/* Copy the accumulated parameter gradient to out[6] (host; synchronises)
+ * and, if reset != 0, zero it.  basis LBM_THETA_NATIVE:
+ * dL/d(kappa, beta, alpha, tau_f, nu_A, nu_B) with the six independent.
+ * basis LBM_THETA_TAU: dL/d(kappa, beta, M, tau_f, tau_gA, tau_gB) with those
+ * six independent, by the chain rule through alpha = M / (c_s^2 (tau_f - 1/2))
+ * (Sec. 2.3.1, eq. mobility) and nu = c_s^2 (tau_g - 1/2) (Sec. 2.3.2), at
+ * the context's parameters.  LBM_EINVAL for another basis. */
+enum { LBM_THETA_NATIVE = 0, LBM_THETA_TAU = 1 };
+int lbm_adjoint_theta(lbm_ctx* ctx, int basis, double* out, int reset);
 
 /* Release the context's host resources (not the caller's buffers). */
 int lbm_destroy(lbm_ctx* ctx);

@@ -14,6 +14,8 @@ LIB_PATH = os.path.join(HERE, "liblbmwb.so")
 LBM_OK, LBM_EINVAL, LBM_EHIP, LBM_ENONFINITE, LBM_ESTATE = 0, -1, -2, -3, -4
 PERIODIC, WALL = 0, 1
 SNAPSHOT_HAS_PHI_MU = 1
+LO_AUTO, LO_16, LO_32 = 0, 1, 2
+THETA_NATIVE, THETA_TAU = 0, 1
 
 # Every symbol include/lbmwb.h declares.
 SYMBOLS = (
@@ -41,12 +43,15 @@ class LbmParams(ctypes.Structure):
         ("diag_every", ctypes.c_int32), ("kernel_path", ctypes.c_int32),
         ("nu_form", ctypes.c_int32), ("collision", ctypes.c_int32),
         ("mrt_f", ctypes.c_double * 4), ("mrt_g", ctypes.c_double * 2),
+        ("lo_format", ctypes.c_int32), ("use_tau", ctypes.c_int32),
+        ("tau_f", ctypes.c_double), ("tau_gA", ctypes.c_double), ("tau_gB", ctypes.c_double),
     ]
 
 
 class LbmDerived(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
-                ("kappa", "beta", "sigma", "W", "tau_f", "tau_gA", "tau_gB", "alpha")]
+                ("kappa", "beta", "sigma", "W", "tau_f", "tau_gA", "tau_gB", "alpha", "nu_A",
+                 "nu_B")] + [("lo16", ctypes.c_int32)]
 
 
 class LbmDiag(ctypes.Structure):
@@ -139,7 +144,7 @@ def load() -> ctypes.CDLL:
     L.lbm_adjoint_segment.restype = ctypes.c_int
     L.lbm_adjoint_init.argtypes = [vp, vp, vp, vp, vp, vp]
     L.lbm_adjoint_init.restype = ctypes.c_int
-    L.lbm_adjoint_theta.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
+    L.lbm_adjoint_theta.argtypes = [vp, ctypes.c_int, ctypes.POINTER(ctypes.c_double), ctypes.c_int]
     L.lbm_adjoint_theta.restype = ctypes.c_int
     _lib = L
     return L

@@ -7,11 +7,10 @@ kernels of the C ABI.  Memory: a raw snapshot every K steps in the forward
 pass; the backward pass recomputes each segment into K snapshots with
 ``lbm_step_into`` (no copies) and walks it in reverse.
 
-theta = (kappa, beta, M, tau_f, tau_gA, tau_gB): the free-energy coefficients
-(Sec. 2.1, eqs. bulk_energy, chemical_potencial), the mobility (Sec. 2.3.1,
-eq. mobility: alpha = M / (c_s^2 (tau_f - 1/2)) follows from M and tau_f),
-and the hydrodynamic relaxation times of the two bulk phases
-(nu = c_s^2 (tau_g - 1/2), Sec. 2.3.2).
+theta = (kappa, beta, M, tau_f, tau_gA, tau_gB): the free-energy coefficients,
+the mobility and the relaxation times, passed to the library as such
+(lbm_params.use_tau); the library derives the rest and returns the gradient
+in this basis (lbm_adjoint_theta with LBM_THETA_TAU).
 """
 from __future__ import annotations
 
@@ -19,30 +18,20 @@ import time
 
 import torch
 
+from . import _lib
 from .sim import Sim
 
 THETA_NAMES = ("kappa", "beta", "M", "tau_f", "tau_gA", "tau_gB")
-CS2 = 1.0 / 3.0
 
 
 def params_from_theta(base, theta):
-    kappa, beta, M, tau_f, tau_gA, tau_gB = (float(v) for v in theta)
+    """A copy of the parameter block ``base`` with theta set (argument
+    marshalling only)."""
     p = type(base).from_buffer_copy(base)
     p.use_sigma_W = 0
-    p.kappa, p.beta, p.M = kappa, beta, M
-    p.alpha = M / (CS2 * (tau_f - 0.5))
-    p.nu_A = CS2 * (tau_gA - 0.5)
-    p.nu_B = CS2 * (tau_gB - 0.5)
+    p.use_tau = 1
+    p.kappa, p.beta, p.M, p.tau_f, p.tau_gA, p.tau_gB = (float(v) for v in theta)
     return p
-
-
-def theta_grad(g6, theta):
-    """Chain rule from the library's (kappa, beta, alpha, tau_f, nu_A, nu_B)."""
-    kappa, beta, M, tau_f, tau_gA, tau_gB = (float(v) for v in theta)
-    gk, gb, ga, gt, gnA, gnB = g6
-    da_dM = 1.0 / (CS2 * (tau_f - 0.5))
-    da_dt = -M / (CS2 * (tau_f - 0.5) ** 2)
-    return [gk, gb, ga * da_dM, gt + ga * da_dt, gnA * CS2, gnB * CS2]
 
 
 class _Rollout(torch.autograd.Function):
@@ -82,12 +71,11 @@ class _Rollout(torch.autograd.Function):
             if sim.adjoint_segment([ckpt[seg]] + snaps[1:L], lam, other) == 1:
                 lam, other = other, lam
         dphi0 = sim.adjoint_init(ckpt[0], phi0, lam, other)
-        g6 = sim.adjoint_theta(reset=True)
+        g6 = sim.adjoint_theta(reset=True, basis=_lib.THETA_TAU)
         torch.cuda.synchronize()
         if ctx.stats is not None:
             ctx.stats["backward_s"] = time.perf_counter() - t0
-            ctx.stats["theta_lib"] = g6
-        gth = torch.tensor(theta_grad(g6, ctx.theta), dtype=torch.float64)
+        gth = torch.tensor(g6, dtype=torch.float64)
         return dphi0 * 1.0, gth, None, None, None, None
 
 

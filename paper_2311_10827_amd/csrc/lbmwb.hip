@@ -82,10 +82,24 @@ int validate(const lbm_params* p, lbm_derived* d) {
   if (pitch * (size_t)p->ny > (size_t)INT32_MAX) return LBM_EINVAL;
   const double dphi = p->phi_A - p->phi_B;
   if (!(dphi != 0.0) || !std::isfinite(dphi)) return LBM_EINVAL;
-  if (!(p->rho_A > 0) || !(p->rho_B > 0) || !(p->nu_A > 0) || !(p->nu_B > 0)) return LBM_EINVAL;
-  if (!(p->M > 0) || !(p->alpha > 0)) return LBM_EINVAL;
-  if (!std::isfinite(p->rho_A) || !std::isfinite(p->rho_B) || !std::isfinite(p->nu_A) ||
-      !std::isfinite(p->nu_B) || !std::isfinite(p->M) || !std::isfinite(p->alpha))
+  if (p->lo_format < LBM_LO_AUTO || p->lo_format > LBM_LO_32) return LBM_EINVAL;
+  if (p->use_tau != 0 && p->use_tau != 1) return LBM_EINVAL;
+  // the relaxation parameters: given (alpha, nu_A, nu_B), or derived from
+  // the given relaxation times by eq. mobility and the viscosity relation of
+  // Sec. 2.3.2, solved for alpha and nu
+  double alpha = p->alpha, nuA = p->nu_A, nuB = p->nu_B;
+  if (p->use_tau) {
+    if (!(p->tau_f > 0.5) || !(p->tau_gA > 0.5) || !(p->tau_gB > 0.5) || !std::isfinite(p->tau_f) ||
+        !std::isfinite(p->tau_gA) || !std::isfinite(p->tau_gB))
+      return LBM_EINVAL;
+    alpha = p->M * INV_CS2 / (p->tau_f - 0.5);
+    nuA = CS2 * (p->tau_gA - 0.5);
+    nuB = CS2 * (p->tau_gB - 0.5);
+  }
+  if (!(p->rho_A > 0) || !(p->rho_B > 0) || !(nuA > 0) || !(nuB > 0)) return LBM_EINVAL;
+  if (!(p->M > 0) || !(alpha > 0)) return LBM_EINVAL;
+  if (!std::isfinite(p->rho_A) || !std::isfinite(p->rho_B) || !std::isfinite(nuA) ||
+      !std::isfinite(nuB) || !std::isfinite(p->M) || !std::isfinite(alpha))
     return LBM_EINVAL;
   if (!std::isfinite(p->gx) || !std::isfinite(p->gy)) return LBM_EINVAL;
   double kappa = p->kappa, beta = p->beta;
@@ -103,12 +117,21 @@ int validate(const lbm_params* p, lbm_derived* d) {
   const double ad = std::fabs(dphi);
   r.sigma = ad * ad * ad * std::sqrt(2.0 * kappa * beta) / 6.0;
   r.W = beta > 0 ? std::sqrt(8.0 * kappa / (beta * dphi * dphi)) : 0.0;
-  r.alpha = p->alpha;
-  // eq. mobility and the viscosity relation of Sec. 2.3.2, solved for tau
-  r.tau_f = 0.5 + p->M * INV_CS2 / p->alpha;
-  r.tau_gA = 0.5 + p->nu_A * INV_CS2;
-  r.tau_gB = 0.5 + p->nu_B * INV_CS2;
+  r.alpha = alpha;
+  r.nu_A = nuA;
+  r.nu_B = nuB;
+  if (p->use_tau) {
+    r.tau_f = p->tau_f;
+    r.tau_gA = p->tau_gA;
+    r.tau_gB = p->tau_gB;
+  } else {
+    // eq. mobility and the viscosity relation of Sec. 2.3.2, solved for tau
+    r.tau_f = 0.5 + p->M * INV_CS2 / alpha;
+    r.tau_gA = 0.5 + nuA * INV_CS2;
+    r.tau_gB = 0.5 + nuB * INV_CS2;
+  }
   if (!(r.tau_f > 0.5) || !(r.tau_gA > 0.5) || !(r.tau_gB > 0.5)) return LBM_EINVAL;
+  r.lo16 = 0;
   if (d) *d = r;
   return LBM_OK;
 }
@@ -140,6 +163,15 @@ constexpr long long FUSED_DISPATCH_ORDER_BLOCKS_32 = 8192;
 // the HBM-bound step from 4096^2 up, 3 % on at 2048^2 where its arithmetic
 // is not hidden
 constexpr size_t LO16_STATE_BYTES = (size_t)1 << 30;
+
+// FP32: the low word of f_0 in 16 bits (lbm_params.lo_format; automatic:
+// for states above LO16_STATE_BYTES, where the 16-bit word pays)
+bool lo16_of(const lbm_params* p, size_t state_bytes) {
+  if (p->precision != 32) return false;
+  if (p->lo_format == LBM_LO_16) return true;
+  if (p->lo_format == LBM_LO_32) return false;
+  return state_bytes > LO16_STATE_BYTES;
+}
 
 size_t adj_plane_bytes(const lbm_params* p) {
   return round_up((size_t)p->nx * p->ny * (p->precision == 32 ? 4 : 8), 256);
@@ -596,7 +628,11 @@ size_t snapshot_bytes(const lbm_ctx* c) {
 
 extern "C" {
 
-int lbm_derive(const lbm_params* p, lbm_derived* out) { return validate(p, out); }
+int lbm_derive(const lbm_params* p, lbm_derived* out) {
+  int r = validate(p, out);
+  if (r == LBM_OK && out) out->lo16 = lo16_of(p, layout_of(p).state_bytes) ? 1 : 0;
+  return r;
+}
 
 size_t lbm_state_bytes(const lbm_params* p) {
   if (validate(p, nullptr) != LBM_OK) return 0;
@@ -677,21 +713,21 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   k.phiB = p->phi_B;
   k.beta4 = 4.0 * d.beta;
   k.kappa = d.kappa;
-  k.alpha = p->alpha;
+  k.alpha = d.alpha;
   k.omega_f = 1.0 / d.tau_f;
   k.rhoB = p->rho_B;
   k.rho_slope = (p->rho_A - p->rho_B) / (p->phi_A - p->phi_B);
-  k.nuB = p->nu_B;
-  k.nu_slope = (p->nu_A - p->nu_B) / (p->phi_A - p->phi_B);
+  k.nuB = d.nu_B;
+  k.nu_slope = (d.nu_A - d.nu_B) / (p->phi_A - p->phi_B);
   k.gx = p->gx;
   k.gy = p->gy;
   k.nu_form = p->nu_form;
   k.dphiAB = p->phi_A - p->phi_B;
-  k.nuA = p->nu_A;
-  k.ln_nuA = std::log(p->nu_A);
-  k.ln_nuB = std::log(p->nu_B);
-  k.inv_nuA = 1.0 / p->nu_A;
-  k.inv_nuB = 1.0 / p->nu_B;
+  k.nuA = d.nu_A;
+  k.ln_nuA = std::log(d.nu_A);
+  k.ln_nuB = std::log(d.nu_B);
+  k.inv_nuA = 1.0 / d.nu_A;
+  k.inv_nuB = 1.0 / d.nu_B;
   k.nu_dphi = p->nu_form == LBM_NU_INVERSE ? (k.inv_nuB - k.inv_nuA) / k.dphiAB
                                            : (k.ln_nuA - k.ln_nuB) / k.dphiAB;
   k.collision = p->collision;
@@ -699,7 +735,8 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   for (int i = 0; i < 2; ++i) k.mg[i] = p->mrt_g[i];
   // the 16-bit low word of f_0 pays where the step is bound by HBM; on
   // smaller states its arithmetic costs more than the bytes it saves
-  c->lo16 = p->precision == 32 && L.state_bytes > LO16_STATE_BYTES;
+  c->lo16 = lo16_of(p, L.state_bytes);
+  c->d.lo16 = c->lo16 ? 1 : 0;
   hipError_t e = hipHostMalloc((void**)&c->diag_host, (2 * NQ + 6) * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
@@ -863,14 +900,25 @@ int lbm_adjoint_init(lbm_ctx* c, const void* state, const double* phi0, const vo
                                         static_cast<float*>(scratch), dphi0);
 }
 
-int lbm_adjoint_theta(lbm_ctx* c, double* out, int reset) {
-  if (!c || !out) return LBM_EINVAL;
+int lbm_adjoint_theta(lbm_ctx* c, int basis, double* out, int reset) {
+  if (!c || !out || (basis != LBM_THETA_NATIVE && basis != LBM_THETA_TAU)) return LBM_EINVAL;
   if (!c->adj) return LBM_ESTATE;
   const long long tiles = (long long)c->ntx2 * c->nty2;
   hipLaunchKernelGGL(k_sum_theta, dim3(1), dim3(256), 0, c->stream, c->th_part, tiles, c->th_out);
   LAUNCHCHK(c);
   HIPCHK(c, hipMemcpyAsync(out, c->th_out, NTH * sizeof(double), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (basis == LBM_THETA_TAU) {
+    // from (kappa, beta, alpha, tau_f, nu_A, nu_B) to (kappa, beta, M,
+    // tau_f, tau_gA, tau_gB): alpha = M / (c_s^2 (tau_f - 1/2)) (eq.
+    // mobility), so d alpha/d M = alpha / M and d alpha/d tau_f at fixed M
+    // = -alpha / (tau_f - 1/2); nu = c_s^2 (tau_g - 1/2) (Sec. 2.3.2)
+    const double a = c->d.alpha, tf = c->d.tau_f, ga = out[2], gt = out[3];
+    out[2] = ga * (a / c->p.M);
+    out[3] = gt - ga * (a / (tf - 0.5));
+    out[4] *= CS2;
+    out[5] *= CS2;
+  }
   if (reset) {
     hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, c->stream, c->th_part, tiles * NTH);
     LAUNCHCHK(c);

@@ -30,7 +30,7 @@ def make_params(workload=None, precision: int = 64, diag_every: int = 0, **over)
               phi_B=-1.0, rho_A=1.0, rho_B=1.0, nu_A=0.1, nu_B=0.1, kappa=0.0, beta=0.0,
               sigma=0.0, W=0.0, M=0.1, alpha=1.0, gx=0.0, gy=0.0, diag_every=diag_every,
               kernel_path=0, nu_form=NU_LINEAR, collision=BGK, mrt_f=(1.0, 1.0, 1.0, 1.0),
-              mrt_g=(1.0, 1.0))
+              mrt_g=(1.0, 1.0), lo_format=_lib.LO_AUTO, use_tau=0, tau_f=0.0, tau_gA=0.0, tau_gB=0.0)
     if workload is not None:
         for k in ("nx", "ny", "bc_x", "bc_y", "phi_A", "phi_B", "rho_A", "rho_B", "nu_A", "nu_B",
                   "sigma", "W", "M", "alpha", "nu_form", "collision", "mrt_f", "mrt_g"):
@@ -287,10 +287,13 @@ class Sim:
         self._keep_phi0 = phi0
         return out
 
-    def adjoint_theta(self, reset: bool = True):
-        """dL/d(kappa, beta, alpha, tau_f, nu_A, nu_B) accumulated so far."""
+    def adjoint_theta(self, reset: bool = True, basis: int = _lib.THETA_NATIVE):
+        """Parameter gradient accumulated so far: dL/d(kappa, beta, alpha, tau_f,
+        nu_A, nu_B) (THETA_NATIVE) or dL/d(kappa, beta, M, tau_f, tau_gA, tau_gB)
+        (THETA_TAU), as the library forms them."""
         buf = (ctypes.c_double * 6)()
-        check(self.L.lbm_adjoint_theta(self.ctx, buf, int(bool(reset))), "lbm_adjoint_theta", self.ctx)
+        check(self.L.lbm_adjoint_theta(self.ctx, int(basis), buf, int(bool(reset))), "lbm_adjoint_theta",
+              self.ctx)
         return list(buf)
 
 

@@ -77,12 +77,48 @@ def test_derive_from_sigma_W():
     dict(gx=float("nan")), dict(kernel_path=3), dict(kernel_path=-1), dict(nu_form=3),
     dict(nu_form=-1), dict(collision=2), dict(collision=1, mrt_f=(0.0, 1.0, 1.0, 1.0)),
     dict(collision=1, mrt_g=(1.0, 2.0)), dict(collision=1, mrt_f=(1.0, 1.0, float("nan"), 1.0)),
+    dict(lo_format=3), dict(lo_format=-1), dict(use_tau=2),
 ])
 def test_derive_rejects(bad):
     p = make_params(inputs.FLAT, **bad)
     rc, _ = _derive(p)
     assert rc == _lib.LBM_EINVAL
     assert _lib.load().lbm_state_bytes(ctypes.byref(p)) == 0
+
+
+def test_derive_from_relaxation_times():
+    # use_tau: alpha from eq. mobility solved for alpha, nu from the viscosity
+    # relation of Sec. 2.3.2; the alpha and nu fields are ignored
+    p = make_params(inputs.DROPLET, use_tau=1, tau_f=0.8, tau_gA=0.53, tau_gB=1.1, alpha=-5.0,
+                    nu_A=-1.0, nu_B=0.0)
+    rc, d = _derive(p)
+    assert rc == 0
+    assert (d.tau_f, d.tau_gA, d.tau_gB) == (0.8, 0.53, 1.1)
+    assert d.alpha == pytest.approx(p.M / ((1 / 3) * 0.3), rel=1e-15)
+    assert d.nu_A == pytest.approx(0.03 / 3, rel=1e-13) and d.nu_B == pytest.approx(0.6 / 3, rel=1e-15)
+    # the same step from (M, alpha, nu) gives the same relaxation times
+    q = make_params(inputs.DROPLET, alpha=d.alpha, nu_A=d.nu_A, nu_B=d.nu_B)
+    rc, e = _derive(q)
+    assert rc == 0
+    for k in ("tau_f", "tau_gA", "tau_gB"):
+        assert getattr(e, k) == pytest.approx(getattr(d, k), rel=1e-15)
+
+
+@pytest.mark.parametrize("bad", [dict(tau_f=0.5), dict(tau_gA=0.4), dict(tau_gB=float("inf")),
+                                 dict(tau_f=float("nan"))])
+def test_derive_rejects_relaxation_times(bad):
+    kw = dict(use_tau=1, tau_f=0.8, tau_gA=0.8, tau_gB=0.8)
+    kw.update(bad)
+    assert _derive(make_params(inputs.DROPLET, **kw))[0] == _lib.LBM_EINVAL
+
+
+@pytest.mark.parametrize("prec,fmt,n,want", [
+    (32, _lib.LO_AUTO, 512, 0), (32, _lib.LO_AUTO, 8192, 1), (32, _lib.LO_16, 512, 1),
+    (32, _lib.LO_32, 8192, 0), (64, _lib.LO_16, 512, 0)])
+def test_low_word_format(prec, fmt, n, want):
+    # automatic: 16 bits above a 1 GiB state (512^2 FP32 is 41 MiB, 8192^2 10 GiB)
+    rc, d = _derive(make_params(inputs.THROUGHPUT, precision=prec, nx=n, ny=n, lo_format=fmt))
+    assert rc == 0 and d.lo16 == want
 
 
 def test_sigma_W_must_be_positive():
@@ -122,3 +158,5 @@ def test_strerror_and_null_context():
     assert L.lbm_step_count(None) == -1
     assert L.lbm_destroy(None) == 0
     assert L.lbm_stream_copy(None, None, 16, None) == _lib.LBM_EINVAL
+    buf = (ctypes.c_double * 6)()
+    assert L.lbm_adjoint_theta(None, _lib.THETA_TAU, buf, 0) == _lib.LBM_EINVAL

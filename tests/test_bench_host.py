@@ -30,7 +30,7 @@ def test_traffic_record_is_consistent():
     for key in ("32", "64"):
         r = rec[key]
         assert bench.measured_traffic(key) == r["bytes_per_launch"] == r["fetch_bytes"] + r["write_bytes"]
-        alg = bench.STEP_BYTES[int(key)] * 16384 * 16384 // 2
+        alg = bench.STEP_IMPL_BYTES[int(key)] * 16384 * 16384 // 2
         assert r["algorithmic_read_bytes"] == r["algorithmic_write_bytes"] == alg
     assert bench.measured_traffic("two_kernel_32") == rec["two_kernel_32"]["bytes_per_step"]
 

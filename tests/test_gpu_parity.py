@@ -135,19 +135,27 @@ def test_fp32_coalescence_crop(path, crop_oracle_1000):
 def test_coalescence_crop_10000_steps():
     # the workload's full 10000 steps on the 512^2 crop, in the step form
     # the library picks at that size: FP64 to 1e-12 relative, FP32 within
-    # 1e-5 in phi and 1e-6 in u of the FP64 oracle
+    # 1e-5 in phi and 1e-6 in u of the FP64 oracle, with the rest
+    # population's low word in either format (the automatic choice keeps it
+    # in an FP32 word at this size; the 16-bit word is what the large
+    # benchmark states run with)
+    from paper_2311_10827_amd import _lib
+    from paper_2311_10827_amd.sim import derive, make_params
     wl, phi0, over = _crop()
     say("[gpu] coalescence crop, 10000 steps: oracle (about a minute on the host)")
     o = oracle_sim(wl, phi0, **over).step(10000)
     ostate, om = o.get_state(), o.moments()
-    for prec in (64, 32):
-        g = gpu_sim(wl, phi0, prec, **over)
+    for prec, fmt in ((64, _lib.LO_AUTO), (32, _lib.LO_AUTO), (32, _lib.LO_16)):
+        lo16 = derive(make_params(wl, precision=prec, lo_format=fmt, **over))["lo16"]
+        assert lo16 == (fmt == _lib.LO_16)
+        g = gpu_sim(wl, phi0, prec, lo_format=fmt, **over)
         g.step(10000)
         gm, d = gpu_moments(g)
         assert d["n_nonfinite"] == 0
         e_phi = np.abs(gm["phi"] - om["phi"]).max()
         e_u = max(np.abs(gm["ux"] - om["ux"]).max(), np.abs(gm["uy"] - om["uy"]).max())
-        say(f"  fp{prec}: phi err {e_phi:.3e}  u err {e_u:.3e}  max|u| {np.hypot(om['ux'], om['uy']).max():.3e}")
+        say(f"  fp{prec} (16-bit low word: {lo16}): phi err {e_phi:.3e}  u err {e_u:.3e}  "
+            f"max|u| {np.hypot(om['ux'], om['uy']).max():.3e}")
         if prec == 64:
             compare_state(gpu_state(g), ostate, TOL64)
             compare_moments(gm, om, TOL64)
@@ -424,14 +432,22 @@ def _full_size_case(name):
     return wl, phi0, pts
 
 
-@pytest.mark.parametrize("prec", [64, 32])
+# MRT rates the benchmark's MRT leg runs with: f (e, eps, q, p), g ((rho, e, eps), q)
+MRT_LEG = dict(collision=1, mrt_f=(1.3, 1.1, 1.6, 1.4), mrt_g=(1.5, 1.7))
+
+
+@pytest.mark.parametrize("prec,coll", [(64, "bgk"), (32, "bgk"), (32, "mrt")])
 @pytest.mark.parametrize("name", ["many_drops_16384", "coalescence_4096"])
-def test_full_size_sampled(name, prec):
-    # A full-size workload in the launch configuration the benchmark times:
+def test_full_size_sampled(name, prec, coll):
+    # A full-size workload in the launch configuration the benchmark times
+    # (FP32 with the MRT collision too, as the benchmark's MRT leg runs it):
     # one and two steps, checked on sampled windows against the oracle run
     # on each window (periodic patch, margin 3 cells per step).
-    say(f"[gpu] full size {name} prec={prec}: generating input")
+    import dataclasses
+    say(f"[gpu] full size {name} prec={prec} {coll}: generating input")
     wl, phi0, pts = _full_size_case(name)
+    if coll == "mrt":
+        wl = dataclasses.replace(wl, **MRT_LEG)
     g = gpu_sim(wl, phi0, prec)
     del phi0
     H = 10
@@ -613,17 +629,18 @@ def test_caller_provided_buffers_bitwise():
         Sim(p, phi0, state=st[: a.state.numel() - 1])
 
 
-@pytest.mark.parametrize("path", PATHS)
-def test_fp32_error_mrt_exp_viscosity_long_run(path):
+@pytest.mark.parametrize("path,lo", [(1, 0), (2, 0), (2, 1)])
+def test_fp32_error_mrt_exp_viscosity_long_run(path, lo):
     # FP32 deviation storage under the MRT collision and the exponential
     # viscosity law over 3000 steps of a walled two-drop field at density
     # ratio 100: phi within 1e-5 and u within 1e-6 of the FP64 oracle
+    # (lo = 1: the rest population's low word forced to 16 bits)
     wl = inputs.Workload("mrt_long", 120, 64, bc_y=1, rho_A=100.0, rho_B=1.0, nu_A=0.01, nu_B=0.1,
                          sigma=2e-3, W=4.0, M=0.05, nu_form=2, **MRT_RATES)
     phi0 = inputs.two_drops(120, 64, 13.0, 3.0, noise=1e-3, workload_id=16)
-    say(f"[gpu] FP32 long run, MRT + exponential viscosity, kernel_path={path}")
+    say(f"[gpu] FP32 long run, MRT + exponential viscosity, kernel_path={path}, lo_format={lo}")
     o = oracle_sim(wl, phi0).step(3000)
-    g32 = gpu_sim(wl, phi0, 32, kernel_path=path)
+    g32 = gpu_sim(wl, phi0, 32, kernel_path=path, lo_format=lo)
     g32.step(3000)
     om = o.moments()
     m32, d32 = gpu_moments(g32)
@@ -637,19 +654,22 @@ def test_fp32_error_mrt_exp_viscosity_long_run(path):
 # FP32 states beyond the last-level cache: 2048 x 1024 (328 MiB: streaming
 # stores, FP32 low word of f_0) and 4096 x 1700 (1.14 GB: streaming stores,
 # 16-bit low word)
-_BIG = {"2048x1024": (2048, 1024, 150.0, False), "4096x1700": (4096, 1700, 250.0, True)}
+# (the 4096 x 1700 state also with the MRT rates of the benchmark's MRT leg)
+_BIG = {"2048x1024": (2048, 1024, 150.0, False, False), "4096x1700": (4096, 1700, 250.0, True, False),
+        "4096x1700_mrt": (4096, 1700, 250.0, True, True)}
 _BIG_STEPS = 60
 
 
-def _big_wl(nx, ny):
-    return inputs.Workload(f"big_fp32_{nx}x{ny}", nx, ny, bc_y=1, rho_A=10.0, rho_B=1.0, nu_A=0.05,
-                           nu_B=0.1, sigma=5e-3, W=4.0, M=0.05)
+def _big_wl(nx, ny, mrt=False):
+    return inputs.Workload(f"big_fp32_{nx}x{ny}{'_mrt' if mrt else ''}", nx, ny, bc_y=1, rho_A=10.0,
+                           rho_B=1.0, nu_A=0.05, nu_B=0.1, sigma=5e-3, W=4.0, M=0.05,
+                           **(MRT_LEG if mrt else {}))
 
 
 @pytest.fixture(scope="module", params=list(_BIG))
 def big_oracle(request):
-    nx, ny, R, lo16 = _BIG[request.param]
-    wl = _big_wl(nx, ny)
+    nx, ny, R, lo16, mrt = _BIG[request.param]
+    wl = _big_wl(nx, ny, mrt)
     phi0 = inputs.two_drops(nx, ny, R, 4.0, noise=1e-3, workload_id=17)
     say(f"[oracle] {nx}x{ny}, {_BIG_STEPS} steps")
     return wl, lo16, phi0, oracle_sim(wl, phi0).step(_BIG_STEPS).moments()
@@ -664,7 +684,8 @@ def test_fp32_state_beyond_cache_against_oracle(path, big_oracle):
     wl, lo16, phi0, om = big_oracle
     nb = _lib.load().lbm_state_bytes(ctypes.byref(make_params(wl, precision=32)))
     assert nb > (224 << 20) and (nb > (1 << 30)) == lo16
-    say(f"[gpu] FP32 {wl.nx}x{wl.ny} (16-bit low word: {lo16}), kernel_path={path}, {_BIG_STEPS} steps")
+    say(f"[gpu] FP32 {wl.nx}x{wl.ny} (16-bit low word: {lo16}), {wl.name}, kernel_path={path}, "
+        f"{_BIG_STEPS} steps")
     g32 = gpu_sim(wl, phi0, 32, kernel_path=path)
     g32.step(_BIG_STEPS)
     m32, d32 = gpu_moments(g32)
