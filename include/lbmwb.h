@@ -251,6 +251,25 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace,
  */
 int lbm_step(lbm_ctx* ctx, int64_t n);
 
+/*
+ * lbm_step for callers that cannot allocate memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * steps, kernels and results as lbm_step, bit for bit, but the diagnostic
+ * reductions of diag_every > 0 use a scratch array the library holds on each
+ * GPU for the life of the process (4 MiB, set up by lbm_init on the GPU
+ * current there) instead of the context's workspace, and the call allocates
+ * nothing.  Limit: a grid whose diagnostic partials, first-level reduction
+ * and result exceed 4 MiB (8 + 1024 + 1 blocks of 11 doubles per strip of
+ * the fused step, or per 64 x 4 tile of the two-kernel step: e.g. 16384^2
+ * fused is 3.0 MB, 4096^2 two-kernel 5.9 MB) gets LBM_EINVAL with the sizes
+ * in lbm_last_error, and no step is taken.  LBM_ESTATE while step timing
+ * (lbm_timing) is on, since it records new events.  LBM_EHIP if lbm_init
+ * could not set the scratch up.  All contexts on one GPU share its scratch:
+ * calls that overlap (different streams, or threads) race on it; calls on
+ * one stream are ordered.  Otherwise as lbm_step.
+ */
+int lbm_step_noalloc(lbm_ctx* ctx, int64_t n);
+
 /* Number of steps taken since lbm_init (or the step given to lbm_set_state). */
 int64_t lbm_step_count(const lbm_ctx* ctx);
 

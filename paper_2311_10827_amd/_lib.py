@@ -24,7 +24,7 @@ SYMBOLS = (
     "lbm_timing", "lbm_kernel_times", "lbm_stream_copy", "lbm_destroy", "lbm_strerror",
     "lbm_last_error", "lbm_snapshot_bytes", "lbm_snapshot", "lbm_restore",
     "lbm_adjoint_workspace_bytes", "lbm_adjoint_attach", "lbm_adjoint_step", "lbm_adjoint_init",
-    "lbm_adjoint_theta", "lbm_step_into", "lbm_adjoint_segment",
+    "lbm_adjoint_theta", "lbm_step_into", "lbm_adjoint_segment", "lbm_step_noalloc",
 )
 
 
@@ -103,6 +103,8 @@ def load() -> ctypes.CDLL:
     L.lbm_init.restype = ctypes.c_int
     L.lbm_step.argtypes = [vp, i64]
     L.lbm_step.restype = ctypes.c_int
+    L.lbm_step_noalloc.argtypes = [vp, i64]
+    L.lbm_step_noalloc.restype = ctypes.c_int
     L.lbm_step_count.argtypes = [vp]
     L.lbm_step_count.restype = i64
     L.lbm_moments.argtypes = [vp, dp, dp, dp, dp, dp, dp, ctypes.POINTER(LbmDiag)]

@@ -14,6 +14,7 @@
 #include <cmath>
 #include <cstdint>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -22,6 +23,40 @@
 #include "lbmwb.h"
 
 using namespace lbm;
+
+// Scratch memory of lbm_step_noalloc, one copy per GPU for the life of the
+// process: the step's diagnostic partials, the first-level reduction and the
+// reduced diagnostics.  Host code never uses this name as an address (it is a
+// host-side stand-in there); the device address comes from
+// hipGetSymbolAddress, once per device, at lbm_init (scratch_on_device).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)4 << 20;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+bool g_scratch_tried[MAX_DEVICES];
+void* g_scratch_ptr[MAX_DEVICES];
+hipError_t g_scratch_err[MAX_DEVICES];
+
+// The device address of `scratch` on device `dev` (current when called the
+// first time for it), or NULL with *err set if the lookup failed.
+void* scratch_on_device(int dev, hipError_t* err) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (dev < 0 || dev >= MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  if (!g_scratch_tried[dev]) {
+    void* ptr = nullptr;
+    g_scratch_err[dev] = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    g_scratch_ptr[dev] = g_scratch_err[dev] == hipSuccess ? ptr : nullptr;
+    g_scratch_tried[dev] = true;
+  }
+  *err = g_scratch_err[dev];
+  return g_scratch_ptr[dev];
+}
+}  // namespace
 
 // ====================================================================== host
 struct lbm_ctx {
@@ -55,6 +90,9 @@ struct lbm_ctx {
   std::vector<hipEvent_t> tev;  // three events per timed step
   std::string err;
   bool u0_zero;         // lbm_init got no initial velocity
+  int device;           // the GPU current at lbm_init
+  double* scratch_dev;  // that GPU's copy of `scratch` (lbm_step_noalloc), or NULL
+  hipError_t scratch_err;
   // adjoint workspace (lbm_adjoint_attach)
   char* adj;
   double* th_part;      // [tiles][NTH] parameter-gradient partials
@@ -653,9 +691,15 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   if (r) return r;
   if (!state || !workspace || !phi0) return LBM_EINVAL;
   if (((uintptr_t)state & 255) || ((uintptr_t)workspace & 255)) return LBM_EINVAL;
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBM_EHIP;
   lbm_ctx* c = new lbm_ctx();
   c->p = *p;
   c->d = d;
+  c->device = dev;
+  // set-up of lbm_step_noalloc's scratch on this device (its failure only
+  // disables that entry point, which then reports it)
+  c->scratch_dev = static_cast<double*>(scratch_on_device(dev, &c->scratch_err));
   const Layout L = layout_of(p);
   c->prec = p->precision;
   c->esz = L.esz;
@@ -768,6 +812,39 @@ int lbm_step(lbm_ctx* c, int64_t n) {
   r = consume_diag(c, false);
   if (r) return r;
   return c->nonfinite ? LBM_ENONFINITE : LBM_OK;
+}
+
+int lbm_step_noalloc(lbm_ctx* c, int64_t n) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0) return LBM_EINVAL;
+  if (c->timing) {
+    c->err = "lbm_step_noalloc: step timing records new events; stop it (lbm_timing 0) first";
+    return LBM_ESTATE;
+  }
+  if (!c->scratch_dev) {
+    c->err = std::string("lbm_step_noalloc: no scratch on this device: hipGetSymbolAddress: ") +
+             hipGetErrorString(c->scratch_err);
+    return LBM_EHIP;
+  }
+  // the step's diagnostic partials (one per strip or tile), the first-level
+  // reduction and the reduced diagnostics, laid out as in the workspace
+  const long long nparts = c->fused ? (long long)c->ntxf * c->ntyf : (long long)c->ntx2 * c->nty2;
+  const size_t need = ((size_t)nparts * NQ + (size_t)RED_BLOCKS * NQ + NQ) * sizeof(double);
+  if (c->p.diag_every > 0 && need > NOALLOC_SCRATCH_BYTES) {
+    c->err = "lbm_step_noalloc: the diagnostics of this grid need " + std::to_string(need) +
+             " bytes of scratch, above its " + std::to_string(NOALLOC_SCRATCH_BYTES) + " bytes";
+    return LBM_EINVAL;
+  }
+  // every kernel below writes these before it reads them: nothing to clear
+  double* const keep[3] = {c->partials, c->red_mid, c->diag_dev};
+  c->partials = c->scratch_dev;
+  c->red_mid = c->partials + (size_t)nparts * NQ;
+  c->diag_dev = c->red_mid + (size_t)RED_BLOCKS * NQ;
+  const int r = lbm_step(c, n);
+  c->partials = keep[0];
+  c->red_mid = keep[1];
+  c->diag_dev = keep[2];
+  return r;
 }
 
 int64_t lbm_step_count(const lbm_ctx* c) { return c ? c->step : -1; }

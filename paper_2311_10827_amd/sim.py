@@ -173,6 +173,12 @@ class Sim:
         check(self.L.lbm_step(self.ctx, int(n)), "lbm_step", self.ctx)
         return self
 
+    def step_noalloc(self, n: int = 1) -> "Sim":
+        """The same steps through lbm_step_noalloc (diagnostic reductions in
+        the library's per-GPU scratch; the call allocates nothing)."""
+        check(self.L.lbm_step_noalloc(self.ctx, int(n)), "lbm_step_noalloc", self.ctx)
+        return self
+
     @property
     def step_count(self) -> int:
         return int(self.L.lbm_step_count(self.ctx))
