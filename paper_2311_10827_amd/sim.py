@@ -183,11 +183,15 @@ class Sim:
     def step_count(self) -> int:
         return int(self.L.lbm_step_count(self.ctx))
 
-    def moments(self, diag: bool = True):
+    def moments(self, diag: bool = True, fields: bool = True):
+        """phi, mu, ux, uy, p, rho as FP64 device fields (fields=False: none,
+        the library stages what its diagnostics need) and, with diag, the
+        FP64 diagnostics under "diag"."""
+        names = ("phi", "mu", "ux", "uy", "p", "rho")
         out = {k: torch.empty(self.shape, dtype=torch.float64, device=self.device)
-               for k in ("phi", "mu", "ux", "uy", "p", "rho")}
+               for k in names} if fields else {}
         d = LbmDiag()
-        rc = self.L.lbm_moments(self.ctx, *(_ptr(out[k]) for k in ("phi", "mu", "ux", "uy", "p", "rho")),
+        rc = self.L.lbm_moments(self.ctx, *(_ptr(out.get(k)) for k in names),
                                 ctypes.byref(d) if diag else None)
         check(rc, "lbm_moments", self.ctx)
         if diag:

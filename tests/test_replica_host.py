@@ -63,4 +63,31 @@ def test_case_parameters():
         wl, _ = replica.workload("flat", 1000.0, mu)
         assert wl.rho_A * wl.nu_A / (wl.rho_B * wl.nu_B) == pytest.approx(mu, rel=1e-15)
     with pytest.raises(ValueError):
-        replica.workload("coalescence", 10.0)
+        replica.workload("bubble", 10.0)
+    with pytest.raises(ValueError):
+        replica.workload("flat", 10.0, 10.0, 0.1)
+
+
+def test_coalescence_case():
+    # Sec. 3.3: 512^2 periodic, R_0 = 0.1 L, centres 0.5 L -+ (R_0 + W/2), W = 8,
+    # the kinematic viscosity ratio nu_l / nu_v given
+    wl, phi0 = replica.workload("coalescence", 1000.0, nu_ratio=0.01)
+    assert phi0.shape == (512, 512) == (wl.ny, wl.nx) and wl.bc_x == wl.bc_y == 0
+    assert (wl.rho_A, wl.rho_B, wl.nu_B) == (1000.0, 1.0, 0.1)
+    assert wl.nu_A == pytest.approx(1e-3, rel=1e-15)
+    assert (wl.sigma, wl.W, wl.M, wl.alpha) == (0.005, 8.0, 0.1, 1.0)
+    R0, c = 51.2, 256.0
+    x1, x2 = c - R0 - 4.0, c + R0 + 4.0
+    row = phi0[256]
+    # each drop's interior is liquid, the far field vapour, and the outer
+    # interfaces sit R_0 from the centres (phi = 1/2 up to the other drop's tail)
+    assert row[int(x1)] > 0.999 and row[int(x2)] > 0.999 and phi0[0, 0] < 1e-12
+    for xe in (x1 - R0, x2 + R0):
+        k = int(round(xe))
+        assert abs(xe - k) < 0.5
+    xs = np.arange(512.0)
+    left = np.interp(0.5, row[:200], xs[:200])   # increasing edge of the left drop
+    assert abs(left - (x1 - R0)) < 1e-3
+    # the centre lies W/2 from both interfaces, so the two diffuse layers
+    # overlap there: phi = 1/2 + 1/2 (1 - 2 tanh(1)) = 1 - tanh(1)
+    assert row[256] == pytest.approx(1.0 - np.tanh(1.0), abs=1e-12)
