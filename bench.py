@@ -376,7 +376,7 @@ def main():
     ap.add_argument("--no-mrt", action="store_true")
     ap.add_argument("--no-coalescence", action="store_true")
     ap.add_argument("--coalescence-steps", type=int, default=1000)
-    ap.add_argument("--place-tries", type=int, default=3,
+    ap.add_argument("--place-tries", type=int, default=5,
                     help="allocations the state placement probe tries (1: take the first)")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-K", type=int, default=100)

@@ -197,6 +197,12 @@ constexpr size_t FUSED_CACHED_STATE_BYTES = (size_t)224 << 20;
 // 16384^2 in FP32 (over three allocations at 16384^2), but 6 % slower at
 // 4096^2 and 3 % at 1024^2 in FP32, and 1.5-3 % slower at 16384^2 in FP64
 constexpr long long FUSED_DISPATCH_ORDER_BLOCKS_32 = 8192;
+// FP32 fused step: resident workgroups per CU (its 48 KB of LDS), and the
+// range of strip heights and the launch size (in rounds of resident
+// workgroups) within which the height is chosen to fill the last round
+constexpr int FUSED32_WG_PER_CU = 3;
+constexpr int FUSED_ROUND_H_MIN = 24, FUSED_ROUND_H_MAX = 48;
+constexpr long long FUSED_FEW_ROUNDS = 4;
 // above this FP32 state size the low word of f_0 is kept in 16 bits: 2 % off
 // the HBM-bound step from 4096^2 up, 3 % on at 2048^2 where its arithmetic
 // is not hidden
@@ -211,13 +217,18 @@ bool lo16_of(const lbm_params* p, size_t state_bytes) {
   return state_bytes > LO16_STATE_BYTES;
 }
 
+// Parameter-gradient partials: one slot per K2 tile of ka_local (ka_mu_phi
+// has no more tiles than that).
+size_t th_tiles(const lbm_params* p) {
+  return (size_t)((p->nx + K2_TX - 1) / K2_TX) * ((p->ny + K2_TY - 1) / K2_TY);
+}
+
 size_t adj_plane_bytes(const lbm_params* p) {
   return round_up((size_t)p->nx * p->ny * (p->precision == 32 ? 4 : 8), 256);
 }
 
 size_t adj_bytes(const lbm_params* p) {
-  const size_t tiles = (size_t)((p->nx + K2_TX - 1) / K2_TX) * ((p->ny + K2_TY - 1) / K2_TY);
-  return ADJ_PLANES * adj_plane_bytes(p) + round_up((tiles + 1) * NTH * sizeof(double), 256);
+  return ADJ_PLANES * adj_plane_bytes(p) + round_up((th_tiles(p) + 1) * NTH * sizeof(double), 256);
 }
 
 Layout layout_of(const lbm_params* p) {
@@ -355,6 +366,13 @@ int launch_fused(lbm_ctx* c, const T* Bin, T* Bout, const T* Sin, T* Sout, T* dp
   return LBM_OK;
 }
 
+// Diagnostic partials one step writes: one per strip of the fused kernels,
+// one per tile of the collide pass.
+long long step_partials(const lbm_ctx* c) {
+  if (c->fused) return (long long)c->ntxf * c->ntyf;
+  return (long long)c->ntx2 * c->nty2;
+}
+
 int launch_reduce(lbm_ctx* c, int slot, long long n) {
   const long long chunk = (n + RED_BLOCKS - 1) / RED_BLOCKS;
   const long long nb = (n + chunk - 1) / chunk;
@@ -447,7 +465,7 @@ int step_impl(lbm_ctx* c, int64_t n) {
     if (diag) {
       int r = consume_diag(c, true);  // the host buffer is about to be reused
       if (r) return r;
-      r = launch_reduce(c, 0, c->fused ? (long long)c->ntxf * c->ntyf : (long long)c->ntx2 * c->nty2);
+      r = launch_reduce(c, 0, step_partials(c));
       if (r) return r;
       HIPCHK(c, hipMemcpyAsync(c->diag_host, c->diag_dev, NQ * sizeof(double),
                                hipMemcpyDeviceToHost, c->stream));
@@ -723,6 +741,31 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
     c->hf = sh;
     c->ntyf = (p->ny + sh - 1) / sh;
     c->fused_xcd = !(p->precision == 32 && (long long)c->ntxf * c->ntyf >= FUSED_DISPATCH_ORDER_BLOCKS_32);
+    // FP32 states beyond the last-level cache whose launch is only a few
+    // rounds of resident workgroups: a strip height that makes the strip
+    // count a whole number of rounds leaves no part-empty last round, and
+    // the strips go in dispatch order (4096^2: 43-row strips, exactly two
+    // rounds, 0.539 against 0.555 ms per step with 32-row strips in XCD
+    // bands on MI355X)
+    int cus = 0;
+    if (p->precision == 32 && L.state_bytes > FUSED_CACHED_STATE_BYTES && sh == Strip<float>::H &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+      const long long slots = (long long)FUSED32_WG_PER_CU * cus;
+      if ((long long)c->ntxf * c->ntyf < FUSED_FEW_ROUNDS * slots) {
+        double best = -1.0;
+        for (int h = FUSED_ROUND_H_MIN; h <= FUSED_ROUND_H_MAX; ++h) {
+          const long long n = (long long)c->ntxf * ((p->ny + h - 1) / h);
+          const double eff = (double)n / (double)(((n + slots - 1) / slots) * slots);
+          const bool closer = std::abs(h - Strip<float>::H) < std::abs(c->hf - Strip<float>::H);
+          if (eff > best + 1e-9 || (eff > best - 1e-9 && closer)) {
+            best = eff;
+            c->hf = h;
+          }
+        }
+        c->ntyf = (p->ny + c->hf - 1) / c->hf;
+        c->fused_xcd = false;
+      }
+    }
   }
   c->ntxm = (p->nx + KM_TX - 1) / KM_TX;
   c->ntym = (p->ny + KM_TY - 1) / KM_TY;
@@ -828,7 +871,7 @@ int lbm_step_noalloc(lbm_ctx* c, int64_t n) {
   }
   // the step's diagnostic partials (one per strip or tile), the first-level
   // reduction and the reduced diagnostics, laid out as in the workspace
-  const long long nparts = c->fused ? (long long)c->ntxf * c->ntyf : (long long)c->ntx2 * c->nty2;
+  const long long nparts = step_partials(c);
   const size_t need = ((size_t)nparts * NQ + (size_t)RED_BLOCKS * NQ + NQ) * sizeof(double);
   if (c->p.diag_every > 0 && need > NOALLOC_SCRATCH_BYTES) {
     c->err = "lbm_step_noalloc: the diagnostics of this grid need " + std::to_string(need) +
@@ -928,7 +971,7 @@ int lbm_adjoint_attach(lbm_ctx* c, void* adj_workspace) {
   if (!c || !adj_workspace || ((uintptr_t)adj_workspace & 255)) return LBM_EINVAL;
   c->adj = static_cast<char*>(adj_workspace);
   c->th_part = reinterpret_cast<double*>(c->adj + ADJ_PLANES * adj_plane_bytes(&c->p));
-  const long long tiles = (long long)c->ntx2 * c->nty2;
+  const long long tiles = (long long)th_tiles(&c->p);
   c->th_out = c->th_part + tiles * NTH;
   hipLaunchKernelGGL(k_zero, dim3(256), dim3(256), 0, c->stream, c->th_part, (tiles + 1) * NTH);
   LAUNCHCHK(c);
@@ -980,7 +1023,7 @@ int lbm_adjoint_init(lbm_ctx* c, const void* state, const double* phi0, const vo
 int lbm_adjoint_theta(lbm_ctx* c, int basis, double* out, int reset) {
   if (!c || !out || (basis != LBM_THETA_NATIVE && basis != LBM_THETA_TAU)) return LBM_EINVAL;
   if (!c->adj) return LBM_ESTATE;
-  const long long tiles = (long long)c->ntx2 * c->nty2;
+  const long long tiles = (long long)th_tiles(&c->p);
   hipLaunchKernelGGL(k_sum_theta, dim3(1), dim3(256), 0, c->stream, c->th_part, tiles, c->th_out);
   LAUNCHCHK(c);
   HIPCHK(c, hipMemcpyAsync(out, c->th_out, NTH * sizeof(double), hipMemcpyDeviceToHost, c->stream));
