@@ -198,10 +198,14 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   const long long n = (long long)p.nx * p.ny;  // plane stride of the dense planes
   const unsigned kd = (unsigned)(y * p.nx + x);  // n <= INT32_MAX
   const C half = C(0.5), one = C(1.0), three = C(3.0);
-  // ---- forward recompute at this cell (FP32 does not read f_0: see below)
+  // ---- forward recompute at this cell (FP32 does not read f_0: see below).
+  // The snapshot is read once per adjoint step and not again until the next
+  // segment's recompute overwrites it: streaming loads, which leave the
+  // last-level cache to the adjoint planes that the next step reads back
+  // (1024^2 FP32: 0.1109 against 0.1124 ms per adjoint step incl. recompute).
   constexpr bool F0 = !std::is_same<T, float>::value;
   Pops<T> q;
-  gather<true, T, true, F0>(B, p, x, y, q);
+  gather<true, T, true, F0, false, true>(B, p, x, y, q);
   Nbhd<T> nb;
   load_nbhd(p, dphi, mupl, x, y, nb);
   const C phi_ref = C(p.phi_ref);

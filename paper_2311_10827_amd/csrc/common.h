@@ -324,13 +324,22 @@ __device__ __forceinline__ short* lo_plane(T* B, const KP& p) {
   return reinterpret_cast<short*>(B + LO_PLANE * p.ps);
 }
 
+// A load, streaming (non-temporal) when NTL.
+template <bool NTL, typename T>
+__device__ __forceinline__ T load_as(const T* ptr) {
+  if constexpr (NTL)
+    return __builtin_nontemporal_load(ptr);
+  else
+    return *ptr;
+}
+
 // WITH_G: also gather g.  WITH_F: gather f (and the low word of f_0);
 // WITH_F0 = false leaves out f_0 and its low word.  LO16: the FP32 low word
-// is stored in 16 bits.
+// is stored in 16 bits.  NTL: streaming loads of the populations.
 // Offsets within a plane fit in 32 bits (pitch * ny <= INT32_MAX); the
 // plane of each load is one of two wave-uniform bases (the direction's own
 // or, for a bounce-back lane, the opposite one).
-template <bool WITH_G, typename T, bool WITH_F = true, bool WITH_F0 = true, bool LO16 = false>
+template <bool WITH_G, typename T, bool WITH_F = true, bool WITH_F0 = true, bool LO16 = false, bool NTL = false>
 __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int x, int y, Pops<T>& q) {
   const PullCols px = pull_cols(x, p.nx, p.bcx);
   const PullCols py = pull_cols(y, p.ny, p.bcy);
@@ -344,11 +353,11 @@ __device__ __forceinline__ void gather(const T* __restrict__ B, const KP& p, int
     const unsigned off = bb ? own : (unsigned)(sy * p.pitch + sx);
     if (WITH_F && (WITH_F0 || i != 0)) {
       const T* pf = bb ? B + opp_of(i) * p.ps : B + i * p.ps;
-      q.f[i] = pf[off];
+      q.f[i] = load_as<NTL>(pf + off);
     }
     if (WITH_G) {
       const T* pg = bb ? B + (9 + opp_of(i)) * p.ps : B + (9 + i) * p.ps;
-      q.g[i] = pg[off];
+      q.g[i] = load_as<NTL>(pg + off);
     }
   }
   if constexpr (WITH_F && WITH_F0 && std::is_same<T, float>::value) {

@@ -4,7 +4,8 @@
   viscosity ratio 100, sigma 1e-3, W 4, M 0.05, 50000 steps): the Laplace
   law and the spurious velocity, in FP64 and in FP32 deviation storage.
 * The paper's flat-interface case (Sec. 3.1): relaxation of the kinetic
-  energy to round-off.
+  energy to round-off, the slow rise after it, and (at density ratio 10,
+  where it completes within a minute) the final decay back to round-off.
 
 At mechanical equilibrium under the potential-form force F = -phi grad mu
 (Sec. 2.1), the quantity that jumps by sigma/R across a 2-D drop is
@@ -84,20 +85,44 @@ def test_laplace_law_and_spurious_velocity(R):
     assert abs(res[32] - res[64]) <= 1e-3 * abs(res[64])
 
 
-def test_paper_flat_interface_relaxes_to_round_off():
+def test_paper_flat_interface_reaches_round_off_before_its_rise():
     # Sec. 3.1: the 32 x 128 liquid slab (phi in {0, 1}) at density ratio
-    # 1000 relaxes from its tanh profile until the total kinetic energy is at
-    # round-off level; the FP64 step is deterministic, so the minimum over the
-    # checkpoints is a fixed number (4.4e-25 with max|u| 1.2e-15 at step
-    # 900000 on MI355X, checkpoints every 1e5 steps).
+    # 1000 relaxes from its tanh profile to a kinetic energy at round-off
+    # level within 1e6 steps (checkpoints every 1e5; the FP64 step is
+    # deterministic: 4.4e-25 with max|u| 1.2e-15 at step 900000 on MI355X).
+    # After that minimum a slow mode grows from round-off (the rise the
+    # paper describes for its slabs): at 1e6 steps E is already above it.
     from paper_2311_10827_amd.replica import relax
     say("[gpu] paper flat interface, density ratio 1000, 1e6 steps")
     hist = relax("flat", 1000.0, 1_000_000, 100_000)
     k = min(range(len(hist)), key=lambda i: hist[i][1])
     step, E, umax, mu_spread = hist[k]
-    say(f"  min E {E:.3e} at step {step}, max|u| {umax:.3e}, mu spread {mu_spread:.3e}")
+    say(f"  min E {E:.3e} at step {step}, max|u| {umax:.3e}, mu spread {mu_spread:.3e}; "
+        f"E at 1e6 steps {hist[-1][1]:.3e}")
     assert E <= 1e-24
     assert umax <= 1e-14
+    assert k < len(hist) - 1 and hist[-1][1] > E
+
+
+def test_paper_flat_interface_rise_and_final_decay():
+    # The whole history the paper describes for its slabs (Sec. 3.1): E
+    # falls, rises (here to O(1e-6), from a mode that grows out of round-off),
+    # and falls again to round-off.  At density ratio 10 that completes
+    # within 6e6 steps (about a minute); the slabs at density ratio 100 and
+    # 1000 take far longer (the recorded histories are in the design notes).
+    from paper_2311_10827_amd.replica import relax
+    say("[gpu] paper flat interface, density ratio 10, 6e6 steps (about a minute)")
+    hist = relax("flat", 10.0, 6_000_000, 200_000, log=say)
+    # (MI355X: 3.2e-19 at 2e5 steps, a peak of 5.2e-7 at 6e5, back at 8.1e-25
+    # by 2.8e6 and at the round-off floor, 1e-31 to 4e-27, from 3e6 on)
+    E = [h[1] for h in hist]
+    peak = max(range(len(E)), key=lambda i: E[i])
+    say(f"  E {E[0]:.3e} at step {hist[0][0]}, peak {E[peak]:.3e} at step {hist[peak][0]}, "
+        f"final {E[-1]:.3e} (max|u| {hist[-1][2]:.3e})")
+    assert E[0] <= 1e-15                                  # fallen from the start
+    assert peak > 0 and E[peak] >= 1e4 * E[0]            # the rise
+    late = hist[len(hist) // 2:]                          # the last 3e6 steps
+    assert max(h[1] for h in late) <= 1e-25 and max(h[2] for h in late) <= 1e-14  # back at round-off
 
 
 def test_paper_flat_interface_relaxes_to_round_off_under_mrt():
