@@ -4,12 +4,14 @@
 Workload: 16384 x 16384 periodic grid, 2000 seeded non-overlapping drops with
 radius ~ U(20, 80), density ratio 100, nu 0.1/0.1, sigma 5e-4, M 0.05, W 4
 (synthetic input; there is no dataset).  One step = phi, mu, both
-collisions and the pull streaming, in the library's fused step kernel,
-through the C ABI.
+collisions and the pull streaming, through the C ABI; the library's
+automatic path runs FP32 steps on this grid two per launch (k_step2, the
+intermediate state kept on chip) and FP64 steps one per launch.
 
 Prints one JSON line: FP32 (deviation storage) MLUPS as the value, the FP64
 step beside it, the roofline of the step kernel measured with HIP events on
-the library's stream, the two-kernel and MRT forms of the FP32 step, the
+the library's stream, the one-step, two-kernel and MRT forms of the FP32
+step, the
 4096^2 two-drop coalescence in both precisions, the adjoint/forward cost
 ratio of the 1024^2 (and 2048^2) inverse problem, and the CPU oracle timed
 on a bounded sample of the workload (the same recipe on a periodic 1024^2
@@ -38,6 +40,8 @@ STEP_BYTES = {32: 2 * 19 * 4, 64: 2 * 19 * 8}
 # of the rest population of f (read and written) that keeps f_0 to about
 # 2^-40; phi and mu stay on chip.
 STEP_IMPL_BYTES = {32: 2 * (18 * 4 + 2 + 4), 64: STEP_BYTES[64]}
+# Two steps per launch: the state read and written once per two steps.
+TWO_STEP_IMPL_BYTES = {32: STEP_IMPL_BYTES[32] / 2}
 # The two-kernel design: the phi/mu pass also reads the 9 f planes and writes
 # phi and mu, and the collide pass reads them back: +(9 + 2 + 2) planes.
 TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (9 + 2 + 2) * 4, 64: STEP_BYTES[64] + (9 + 2 + 2) * 8}
@@ -61,9 +65,10 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(key: str):
-    """HBM bytes per launch of the fused step kernel ("32", "64"), or per step
-    of the two-kernel path ("two_kernel_32"), from the committed rocprofv3
-    counter summary, if it was taken on the current kernel source."""
+    """HBM bytes per launch of a step kernel ("two_step_32": two steps; "32",
+    "64": one step), or per step of the two-kernel path ("two_kernel_32"),
+    from the committed rocprofv3 counter summary, if it was taken on the
+    current kernel source."""
     try:
         with open(TRAFFIC_FILE) as fh:
             t = json.load(fh)
@@ -79,17 +84,21 @@ def measured_traffic(key: str):
 MRT_LEG = dict(collision=1, mrt_f=(1.3, 1.1, 1.6, 1.4), mrt_g=(1.5, 1.7))
 
 
-def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl, kernel_path: int = 2,
+def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl, kernel_path: int = 0,
             mrt: bool = False, bufs=None):
+    """kernel_path 0: the library's choice (two steps per launch for FP32
+    here), 2: one fused step per launch, 1: the two-kernel step."""
     import torch
-    from paper_2311_10827_amd.sim import Sim, make_params
+    from paper_2311_10827_amd.sim import Sim, derive, make_params
 
     p = make_params(wl, precision=prec, kernel_path=kernel_path, **(MRT_LEG if mrt else {}))
+    per_launch = 2 if derive(p)["two_step"] else 1
     state, ws = bufs if bufs is not None else (None, None)
     sim = Sim(p, phi0_dev, device=phi0_dev.device, state=state, workspace=ws)
     stream = sim.stream
     ncell = wl.nx * wl.ny
-    tag = f"fp{prec}{'' if kernel_path == 2 else ' two-kernel'}{' MRT' if mrt else ''}"
+    form = {1: "two-kernel", 2: "one-step"}.get(kernel_path, "two-step" if per_launch == 2 else "one-step")
+    tag = f"fp{prec} {form}{' MRT' if mrt else ''}"
     log(f"[bench] {tag}: warmup {warmup}")
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -114,16 +123,24 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
     sim.close()
     del sim
     torch.cuda.empty_cache()
-    avg = kms / n
-    alg = STEP_BYTES[prec] if kernel_path == 2 else TWO_KERNEL_BYTES[prec]
-    impl = STEP_IMPL_BYTES[prec] if kernel_path == 2 else TWO_KERNEL_IMPL_BYTES[prec]
+    avg = kms / n  # ms per step
+    if kernel_path == 1:
+        alg, impl, key = TWO_KERNEL_BYTES[prec], TWO_KERNEL_IMPL_BYTES[prec], f"two_kernel_{prec}"
+    elif per_launch == 2:
+        alg, impl, key = STEP_BYTES[prec], TWO_STEP_IMPL_BYTES[prec], f"two_step_{prec}"
+    else:
+        alg, impl, key = STEP_BYTES[prec], STEP_IMPL_BYTES[prec], str(prec)
+    # algorithmic bytes per launch (steps per launch x cells x bytes per
+    # cell update) over the launch's duration
     ach = alg * ncell / (avg * 1e-3) / 1e9
-    traffic = None if mrt else measured_traffic(str(prec) if kernel_path == 2 else f"two_kernel_{prec}")
+    traffic = None if mrt else measured_traffic(key)
+    launch_ms = avg * (per_launch if kernel_path != 1 else 1)
     return {
         "mlups": ncell * steps / (ms * 1e-3) / 1e6,
         "ms_per_step": ms / steps,
         "wall_s": wall,
         "kernel_ms": avg,
+        "steps_per_launch": per_launch if kernel_path != 1 else 1,
         "algorithmic_bytes_per_cell": alg,
         "implementation_bytes_per_cell": impl,
         "implementation_GBps": round(impl * ncell / (avg * 1e-3) / 1e9, 1),
@@ -135,10 +152,10 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
             "frac": round(ach / HBM_PEAK_GBPS, 4),
             "traffic": traffic,
         },
-        # the counted HBM bytes (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)
-        # over the same live kernel time
+        # the counted HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+        # calibrated) over the same live launch time
         "measured_bytes_frac": None if traffic is None
-        else round(traffic / (avg * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        else round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
         "diag_after": {k: d[k] for k in ("sum_phi", "max_u", "min_rho", "n_nonfinite", "step")},
     }
 
@@ -373,6 +390,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-two-kernel", action="store_true")
+    ap.add_argument("--no-one-step", action="store_true")
     ap.add_argument("--no-mrt", action="store_true")
     ap.add_argument("--no-coalescence", action="store_true")
     ap.add_argument("--coalescence-steps", type=int, default=1000)
@@ -422,6 +440,10 @@ def main():
                                                    tries=args.place_tries)
     bufs32 = (st32, ws32)
     r32 = run_gpu(phi0_dev, 32, args.steps, args.warmup, args.kernel_steps, wl, bufs=bufs32)
+    r1s = None
+    if not args.no_one_step:
+        r1s = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, kernel_path=2,
+                      bufs=bufs32)
     r2k = None
     if not args.no_two_kernel:
         r2k = run_gpu(phi0_dev, 32, max(args.steps // 4, 10), args.warmup, args.kernel_steps, wl, kernel_path=1,
@@ -468,6 +490,7 @@ def main():
         },
         "roofline": r32["roofline"],
         "measured_bytes_frac": r32["measured_bytes_frac"],
+        "steps_per_launch": r32["steps_per_launch"],
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
         "kernel_ms": round(r32["kernel_ms"], 4),
@@ -484,6 +507,13 @@ def main():
             "algorithmic_bytes_per_cell": r64["algorithmic_bytes_per_cell"],
             "roofline": r64["roofline"], "measured_bytes_frac": r64["measured_bytes_frac"],
         },
+        "one_step_fp32": None if r1s is None else {
+            "value": round(r1s["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r1s["ms_per_step"], 4),
+            "kernel_ms": round(r1s["kernel_ms"], 4),
+            "algorithmic_bytes_per_cell": r1s["algorithmic_bytes_per_cell"],
+            "implementation_bytes_per_cell": r1s["implementation_bytes_per_cell"], "roofline": r1s["roofline"],
+            "measured_bytes_frac": r1s["measured_bytes_frac"],
+        },
         "two_kernel_fp32": None if r2k is None else {
             "value": round(r2k["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(r2k["ms_per_step"], 4),
             "algorithmic_bytes_per_cell": r2k["algorithmic_bytes_per_cell"],
@@ -494,6 +524,7 @@ def main():
             "value": round(rmrt["mlups"], 1), "unit": "MLUPS", "ms_per_step": round(rmrt["ms_per_step"], 4),
             "kernel_ms": round(rmrt["kernel_ms"], 4),
             "algorithmic_bytes_per_cell": rmrt["algorithmic_bytes_per_cell"],
+            "steps_per_launch": rmrt["steps_per_launch"],
             "roofline": rmrt["roofline"], "rates": {"f": MRT_LEG["mrt_f"], "g": MRT_LEG["mrt_g"]},
         },
         "fp32_fp64_ratio": None if r64 is None else round(r32["mlups"] / r64["mlups"], 3),

@@ -95,12 +95,19 @@ enum { LBM_LO_AUTO = 0, LBM_LO_16 = 1, LBM_LO_32 = 2 };
  *                      from the rest equilibrium; diagnostics stay FP64.
  *   diag_every     0: no diagnostics inside lbm_step; k > 0: a fused FP64
  *                  diagnostic pass every k steps (see lbm_step).
- *   kernel_path    0: automatic: the fused kernel when the grid gives its
- *                  launch enough workgroups (at least 512 strips of 256 x 8
- *                  cells), else the two kernels;
+ *   kernel_path    0: automatic: two steps per launch (as 3) for an FP32
+ *                  state on a periodic grid that does not fit the GPU's
+ *                  last-level cache; else the fused kernel when the grid
+ *                  gives its launch enough workgroups (at least 512 strips
+ *                  of 256 x 8 cells), else the two kernels;
  *                  1: the phi/mu pass and the collide-stream pass as two
  *                  kernels; 2: one fused kernel per step (phi and mu kept
- *                  on chip).  All give the same results bit for bit.
+ *                  on chip); 3: two steps per launch (the intermediate
+ *                  state kept on chip, only every second state written to
+ *                  memory), FP32 on grids periodic in both directions
+ *                  only; a step due for diagnostics, and the last of an
+ *                  odd count, runs as in 2.  All give the same results bit
+ *                  for bit.
  *   nu_form        how nu varies across the interface (Sec. 2.3.2).  With the
  *                  phase-A fraction s = (phi - phi_B)/(phi_A - phi_B):
  *                  LBM_NU_LINEAR:  nu linear in phi (eq. vis, the paper's
@@ -168,6 +175,10 @@ typedef struct lbm_derived {
   double alpha;           /* as given, or M / (c_s^2 (tau_f - 1/2)) (use_tau) */
   double nu_A, nu_B;      /* as given, or c_s^2 (tau_g - 1/2) (use_tau) */
   int32_t lo16;           /* 1 if an FP32 state keeps the low word in 16 bits */
+  int32_t two_step;       /* 1 if lbm_step runs two steps per launch where it
+                           * can (kernel_path 3, or 0 for an FP32 state on a
+                           * grid periodic in both directions larger than the
+                           * GPU's last-level cache) */
 } lbm_derived;
 
 /*
@@ -213,14 +224,14 @@ typedef struct lbm_ctx lbm_ctx;
  * than 2^31 - 1 cells; bc not 0/1; precision not 32/64; phi_A == phi_B;
  * rho_A, rho_B <= 0; nu_A, nu_B <= 0; M <= 0; alpha <= 0; kappa or beta
  * < 0 (or sigma, W <= 0 with use_sigma_W); diag_every < 0; kernel_path not
- * 0..2; nu_form not one of LBM_NU_*; collision not LBM_BGK or LBM_MRT; with
+ * 0..3, or 3 with precision 64 or a wall; nu_form not one of LBM_NU_*; collision not LBM_BGK or LBM_MRT; with
  * LBM_MRT, an MRT rate outside (0, 2); lo_format not one of LBM_LO_*;
  * use_tau not 0/1; with use_tau, a relaxation time <= 1/2 or not finite. */
 int lbm_derive(const lbm_params* p, lbm_derived* out);
 
 /* Bytes the caller must allocate for the state and the workspace (0 if `p`
- * is invalid).  The state holds two population buffers and the phi, mu and
- * source planes; its layout is private to the library (256-byte aligned
+ * is invalid).  The state holds two population buffers, two source planes
+ * (S_prev, and S of a two-step launch) and the phi and mu planes; its layout is private to the library (256-byte aligned
  * planes).  The workspace holds reduction partials. */
 size_t lbm_state_bytes(const lbm_params* p);
 size_t lbm_workspace_bytes(const lbm_params* p);

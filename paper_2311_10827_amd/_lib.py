@@ -51,7 +51,7 @@ class LbmParams(ctypes.Structure):
 class LbmDerived(ctypes.Structure):
     _fields_ = [(k, ctypes.c_double) for k in
                 ("kappa", "beta", "sigma", "W", "tau_f", "tau_gA", "tau_gB", "alpha", "nu_A",
-                 "nu_B")] + [("lo16", ctypes.c_int32)]
+                 "nu_B")] + [("lo16", ctypes.c_int32), ("two_step", ctypes.c_int32)]
 
 
 class LbmDiag(ctypes.Structure):

@@ -89,6 +89,9 @@ __device__ __forceinline__ C mu_cell(const KP& p, const C (&v)[3][3]) {
     const double lap = lap_f64(v);
     return (((p.beta4 * (ph - p.phiA)) * (ph - p.phiB)) * (ph - p.phim)) - p.kappa * lap;
   } else {
+    // FP32: a * b + c may fuse (each such expression as written, so every
+    // FP32 kernel gets the same bits)
+#pragma clang fp contract(on)
     const C axis = ((v[1][2] - c) + (v[1][0] - c)) + ((v[2][1] - c) + (v[0][1] - c));
     const C diag = ((v[2][2] - c) + (v[2][0] - c)) + ((v[0][2] - c) + (v[0][0] - c));
     const C lap = (C)(2.0 / 3.0) * axis + (C)(1.0 / 6.0) * diag;
@@ -276,6 +279,9 @@ template <bool WRITE, bool MRT = false>
 __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, const Nbhd<float>& n,
                                          float Sp, float (&fo)[9], float& fo_lo, float (&go)[9],
                                          CellOut& out) {
+  // a * b + c may fuse (each such expression as written, so every FP32
+  // kernel gets the same bits); the TwoSum of f_0 has no products
+#pragma clang fp contract(on)
   const float third = (float)(1.0 / 3.0), twelfth = (float)(1.0 / 12.0);
   const auto& ph = n.ph;
   const auto& m = n.mu;
@@ -295,7 +301,7 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
   const float mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
   const float my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
   const float gnz = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
-  const float irho = 1.0f / rho;
+  const float irho = __builtin_amdgcn_rcpf(rho);  // the hardware reciprocal (1 ulp)
   const float ux = (mx + 0.5f * Fx) * irho, uy = (my + 0.5f * Fy) * irho;
   const float uu = ux * ux + uy * uy;
   const float ugr = ux * grx + uy * gry;
@@ -340,23 +346,37 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
     if constexpr (MRT) fo[i] += corr_f[i];
   }
   const float tau = 0.5f + 3.0f * visc<float>(p, dB);
-  const float wg = 1.0f / tau;
+  const float wg = __builtin_amdgcn_rcpf(tau);
   const float kG = 1.0f - 0.5f * wg;
   const float ge0 = -(float)(5.0 / 3.0) * pr - (float)(2.0 / 3.0) * rho * uu;
   go[0] = g[0] + wg * (ge0 - g[0]);
   float z[9];  // MRT: (g^eq - g) - G~/2
   if constexpr (MRT) z[0] = ge0 - g[0];  // G~_0 vanishes: its u.grad(rho) terms cancel
   const float p3 = 3.0f * pr, ruu = 1.5f * rho * uu;
+  // Directions in opposite pairs (i, opp(i)), c_opp = -c_i: with s the part
+  // of g^eq_i and of the forcing G~_i even in c_i and a the odd part,
+  //   g^eq = w (3p - 1.5 rho u.u + 4.5 rho (c.u)^2) + w 3 rho (c.u),
+  //   G~   = 3 kG w (c.u)(c.grad rho) + 3 kG w (c.F),
+  // and g_out = g + wg (g^eq - g) + G~ = (1 - wg) g + (wg s_eq + s_G) +- (wg a_eq + a_G).
+  const float keep = 1.0f - wg;
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
+    if (i != 1 && i != 2 && i != 5 && i != 6) continue;  // i: 1 E, 2 N, 5 NE, 6 NW; opp 3, 4, 7, 8
+    const int j = opp_of(i);
     const float cu = (float)cx_of(i) * ux + (float)cy_of(i) * uy;
     const float cF = (float)cx_of(i) * Fx + (float)cy_of(i) * Fy;
     const float cr = (float)cx_of(i) * grx + (float)cy_of(i) * gry;
     const float w = (float)w_of(i);
-    const float geq = w * (p3 + rho * (cu * (3.0f + 4.5f * cu)) - ruu);
-    const float Gi = kG * 3.0f * w * (cF + cu * cr);
-    go[i] = g[i] + wg * (geq - g[i]) + Gi;
-    if constexpr (MRT) z[i] = (geq - g[i]) - 1.5f * w * (cF + cu * cr);
+    const float s_eq = w * (p3 - ruu + 4.5f * rho * (cu * cu)), a_eq = (3.0f * w) * (rho * cu);
+    const float s_G = (3.0f * w) * kG * (cu * cr), a_G = (3.0f * w) * kG * cF;
+    const float A = wg * s_eq + s_G, B = wg * a_eq + a_G;
+    go[i] = keep * g[i] + A + B;
+    go[j] = keep * g[j] + A - B;
+    if constexpr (MRT) {
+      const float s_z = s_eq - (1.5f * w) * (cu * cr), a_z = a_eq - (1.5f * w) * cF;
+      z[i] = (s_z + a_z) - g[i];
+      z[j] = (s_z - a_z) - g[j];
+    }
   }
   if constexpr (MRT) {
     float corr[9];

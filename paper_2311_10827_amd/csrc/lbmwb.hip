@@ -20,6 +20,7 @@
 
 #include "adjoint.h"
 #include "forward.h"
+#include "step2.h"
 #include "lbmwb.h"
 
 using namespace lbm;
@@ -69,6 +70,7 @@ struct lbm_ctx {
   char* ws;
   hipStream_t stream;
   int cur;
+  int scur;             // which of the two S planes holds S_prev
   int64_t step;
   int ntx1, nty1, ntx2, nty2;
   int ntxf, ntyf, hf;   // strips of the fused step kernel and their height
@@ -78,6 +80,9 @@ struct lbm_ctx {
   int ntxm, ntym;       // tiles of ka_mu_phi (no more than the K2 tiles, whose
                         // count sizes the parameter partials)
   bool fused;           // lbm_step runs the fused kernel
+  bool two_step;        // lbm_step runs pairs of steps as one k_step2 launch
+  int w2s, ntx2s, nty2s, h2s; // strips of k_step2: width, counts, height
+  bool s2_xcd;          // k_step2 deals its strips to XCDs in contiguous bands
   double* partials;
   double* red_mid;      // [RED_BLOCKS][NQ]: first-level reduction results
   double* diag_dev;     // [2][NQ]: fused step diagnostics, moments diagnostics; then
@@ -87,7 +92,8 @@ struct lbm_ctx {
   bool diag_pending, diag_seen, nonfinite;
   hipEvent_t diag_ev;
   bool timing;
-  std::vector<hipEvent_t> tev;  // three events per timed step
+  std::vector<hipEvent_t> tev;  // two events per timed launch
+  std::vector<int> tev_steps;   // steps each timed launch advanced
   std::string err;
   bool u0_zero;         // lbm_init got no initial velocity
   int device;           // the GPU current at lbm_init
@@ -109,7 +115,9 @@ int validate(const lbm_params* p, lbm_derived* d) {
   if (p->bc_x < 0 || p->bc_x > 1 || p->bc_y < 0 || p->bc_y > 1) return LBM_EINVAL;
   if (p->precision != 32 && p->precision != 64) return LBM_EINVAL;
   if (p->diag_every < 0) return LBM_EINVAL;
-  if (p->kernel_path < 0 || p->kernel_path > 2) return LBM_EINVAL;
+  if (p->kernel_path < 0 || p->kernel_path > 3) return LBM_EINVAL;
+  // two steps per launch: FP32 on grids periodic in both directions
+  if (p->kernel_path == 3 && (p->precision != 32 || p->bc_x != 0 || p->bc_y != 0)) return LBM_EINVAL;
   if (p->nu_form < LBM_NU_LINEAR || p->nu_form > LBM_NU_EXP) return LBM_EINVAL;
   if (p->collision != LBM_BGK && p->collision != LBM_MRT) return LBM_EINVAL;
   if (p->collision == LBM_MRT) {
@@ -170,6 +178,7 @@ int validate(const lbm_params* p, lbm_derived* d) {
   }
   if (!(r.tau_f > 0.5) || !(r.tau_gA > 0.5) || !(r.tau_gB > 0.5)) return LBM_EINVAL;
   r.lo16 = 0;
+  r.two_step = 0;
   if (d) *d = r;
   return LBM_OK;
 }
@@ -197,6 +206,15 @@ constexpr size_t FUSED_CACHED_STATE_BYTES = (size_t)224 << 20;
 // 16384^2 in FP32 (over three allocations at 16384^2), but 6 % slower at
 // 4096^2 and 3 % at 1024^2 in FP32, and 1.5-3 % slower at 16384^2 in FP64
 constexpr long long FUSED_DISPATCH_ORDER_BLOCKS_32 = 8192;
+// k_step2 launches aim at no fewer workgroups than this (two rounds of two
+// per CU): at 4096^2, 64-row strips (1216 workgroups) take 0.481 ms per
+// step on MI355X, 32-row strips 0.489 ms and 128-row strips (608) 0.589 ms;
+// at 16384^2 the 128-row strips are 3 % faster than 64-row ones
+constexpr long long S2_MIN_BLOCKS = 1024;
+// k_step2: resident workgroups per CU (its ~200 VGPRs), and the lowest
+// strip height the round-filling choice considers
+constexpr int S2_WG_PER_CU = 2;
+constexpr int S2_ROUND_H_MIN = 48;
 // FP32 fused step: resident workgroups per CU (its 48 KB of LDS), and the
 // range of strip heights and the launch size (in rounds of resident
 // workgroups) within which the height is chosen to fill the last round
@@ -215,6 +233,18 @@ bool lo16_of(const lbm_params* p, size_t state_bytes) {
   if (p->lo_format == LBM_LO_16) return true;
   if (p->lo_format == LBM_LO_32) return false;
   return state_bytes > LO16_STATE_BYTES;
+}
+
+// Two steps per launch (k_step2): asked for (kernel_path 3), or automatic
+// for FP32 states on periodic grids beyond the last-level cache (measured on
+// MI355X, against the fused single step: 16384^2 5.92 against 7.50 ms per
+// step, 8192^2 1.93 against 2.11, 4096^2 0.461 against 0.533, 2048^2 equal;
+// at 1024^2, where the single step runs from the cache, 0.050 against
+// 0.039 ms)
+bool two_step_of(const lbm_params* p, size_t state_bytes) {
+  if (p->kernel_path == 3) return true;
+  return p->kernel_path == 0 && p->precision == 32 && p->bc_x == 0 && p->bc_y == 0 &&
+         state_bytes > FUSED_CACHED_STATE_BYTES;
 }
 
 // Parameter-gradient partials: one slot per K2 tile of ka_local (ka_mu_phi
@@ -239,7 +269,9 @@ Layout layout_of(const lbm_params* p) {
   // Plane stride: 256-byte multiple plus 4 KiB of padding so that the 18
   // planes read together do not sit at addresses a power of two apart.
   L.ps = round_up(L.pitch * (size_t)p->ny, 256 / L.esz) + 4096 / L.esz;
-  L.state_bytes = (2 * L.nb + 3) * L.ps * L.esz;
+  // two population buffers, two S planes (k_step2 reads one and writes the
+  // other), the phi and mu planes
+  L.state_bytes = (2 * L.nb + 4) * L.ps * L.esz;
   L.ntx1 = (p->nx + K1_TX - 1) / K1_TX;
   L.nty1 = (p->ny + K1_TY - 1) / K1_TY;
   L.ntx2 = (p->nx + K2_TX - 1) / K2_TX;
@@ -271,11 +303,13 @@ T* popbuf(lbm_ctx* c, int which) {
   return plane<T>(c, which * Store<T>::NB);
 }
 template <typename T>
-T* S_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB); }
+T* S_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + c->scur); }
 template <typename T>
-T* dphi_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + 1); }
+T* S_alt(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + (c->scur ^ 1)); }
 template <typename T>
-T* mu_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + 2); }
+T* dphi_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + 2); }
+template <typename T>
+T* mu_plane(lbm_ctx* c) { return plane<T>(c, 2 * Store<T>::NB + 3); }
 
 unsigned blocks_for(long long n) { return (unsigned)((n + 255) / 256); }
 
@@ -444,23 +478,66 @@ int launch_step(lbm_ctx* c, bool diag) {
   return diag ? launch_collide<T, M_STEP_DIAG>(c, MomOut{}) : launch_collide<T, M_STEP>(c, MomOut{});
 }
 
+// Two steps as one k_step2 launch (FP32, periodic): the state advances by
+// two steps and S moves to the other S plane.
+template <bool MRT, bool NT>
+void launch_step2_k(lbm_ctx* c, const float* Bin, float* Bout, const float* Sin, float* Sout) {
+  lo_dispatch<float>(c, [&](auto lo) {
+    constexpr bool L16 = decltype(lo)::value;
+    hipLaunchKernelGGL((k_step2<MRT, NT, L16>), dim3(c->ntx2s * c->nty2s), dim3(S2_L), 0, c->stream, c->kp,
+                       Bin, Bout, Sin, Sout, c->w2s, c->ntx2s, c->h2s, c->s2_xcd ? 1 : 0);
+  });
+}
+int launch_step2(lbm_ctx* c) {
+  const float* Bin = popbuf<float>(c, c->cur);
+  float* Bout = popbuf<float>(c, c->cur ^ 1);
+  const float* Sin = S_plane<float>(c);
+  float* Sout = S_alt<float>(c);
+  const bool mrt = c->kp.collision == LBM_MRT;
+  if (c->fused_nt) {
+    if (mrt)
+      launch_step2_k<true, true>(c, Bin, Bout, Sin, Sout);
+    else
+      launch_step2_k<false, true>(c, Bin, Bout, Sin, Sout);
+  } else {
+    if (mrt)
+      launch_step2_k<true, false>(c, Bin, Bout, Sin, Sout);
+    else
+      launch_step2_k<false, false>(c, Bin, Bout, Sin, Sout);
+  }
+  LAUNCHCHK(c);
+  return LBM_OK;
+}
+
 template <typename T>
 int step_impl(lbm_ctx* c, int64_t n) {
   for (int64_t k = 0; k < n; ++k) {
     const bool diag = c->p.diag_every > 0 && (c->step % c->p.diag_every) == 0;
+    // two steps in one launch when neither is due for diagnostics
+    const bool pair = std::is_same<T, float>::value && c->two_step && k + 1 < n && !diag &&
+                      !(c->p.diag_every > 0 && ((c->step + 1) % c->p.diag_every) == 0);
+    auto launch = [&]() { return pair ? launch_step2(c) : launch_step<T>(c, diag); };
     if (c->timing) {
       hipEvent_t e[2];
       for (int j = 0; j < 2; ++j) {
         HIPCHK(c, hipEventCreate(&e[j]));
         c->tev.push_back(e[j]);
       }
+      c->tev_steps.push_back(pair ? 2 : 1);
       HIPCHK(c, hipEventRecord(e[0], c->stream));
-      int r = launch_step<T>(c, diag);
+      int r = launch();
       if (r) return r;
       HIPCHK(c, hipEventRecord(e[1], c->stream));
     } else {
-      int r = launch_step<T>(c, diag);
+      int r = launch();
       if (r) return r;
+    }
+    if (pair) {
+      c->cur ^= 1;
+      c->scur ^= 1;
+      c->step += 2;
+      k += 1;
+      continue;
     }
     if (diag) {
       int r = consume_diag(c, true);  // the host buffer is about to be reused
@@ -686,7 +763,10 @@ extern "C" {
 
 int lbm_derive(const lbm_params* p, lbm_derived* out) {
   int r = validate(p, out);
-  if (r == LBM_OK && out) out->lo16 = lo16_of(p, layout_of(p).state_bytes) ? 1 : 0;
+  if (r == LBM_OK && out) {
+    out->lo16 = lo16_of(p, layout_of(p).state_bytes) ? 1 : 0;
+    out->two_step = two_step_of(p, layout_of(p).state_bytes) ? 1 : 0;
+  }
   return r;
 }
 
@@ -725,6 +805,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   c->ws = static_cast<char*>(workspace);
   c->stream = static_cast<hipStream_t>(stream);
   c->cur = 0;
+  c->scur = 0;
   c->step = 0;
   c->ntx1 = L.ntx1;
   c->nty1 = L.nty1;
@@ -776,8 +857,47 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
     // (measured crossover: between 768^2 and 1024^2 in both precisions).
     const long long strips8 = (long long)c->ntxf * ((p->ny + 7) / 8);
     const long long need = p->precision == 32 ? FUSED_AUTO_STRIPS_32 : FUSED_AUTO_STRIPS_64;
-    c->fused = p->kernel_path == 2 || (p->kernel_path == 0 && strips8 >= need);
+    c->fused = p->kernel_path >= 2 || (p->kernel_path == 0 && strips8 >= need);
     c->fused_nt = L.state_bytes > FUSED_CACHED_STATE_BYTES;
+  }
+  {
+    // k_step2 strips.  Width: 224 or 240 columns (whole 64-byte segments of
+    // a row), whichever leaves fewer of the 256 lanes per row idle (16384^2
+    // on MI355X: 240 columns, 5.92 against 6.25 ms per step).  Height: S2_H
+    // rows, halved (down to 16) while the launch has fewer than
+    // S2_MIN_BLOCKS workgroups; a launch of only a few rounds of resident
+    // workgroups takes the height in [S2_ROUND_H_MIN, S2_H] that fills its
+    // last round best.
+    c->two_step = two_step_of(p, L.state_bytes);
+    auto lanes_used = [&](int w) {
+      return (double)p->nx / ((double)((p->nx + w - 1) / w) * S2_L);
+    };
+    c->w2s = lanes_used(240) >= lanes_used(224) ? 240 : 224;
+    c->ntx2s = (p->nx + c->w2s - 1) / c->w2s;
+    int h = S2_H;
+    while (h > 16 && (long long)c->ntx2s * ((p->ny + h - 1) / h) < S2_MIN_BLOCKS) h /= 2;
+    int cus = 0;
+    if (h >= S2_ROUND_H_MIN &&
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0) {
+      const long long slots = (long long)S2_WG_PER_CU * cus;
+      if ((long long)c->ntx2s * ((p->ny + h - 1) / h) < FUSED_FEW_ROUNDS * slots) {
+        double best = -1.0;
+        int hb = h;
+        for (int hh = S2_ROUND_H_MIN; hh <= S2_H; ++hh) {
+          const long long n = (long long)c->ntx2s * ((p->ny + hh - 1) / hh);
+          if (n < slots) continue;  // at least one full round
+          const double eff = (double)n / (double)(((n + slots - 1) / slots) * slots);
+          if (eff > best + 1e-9 || (eff > best - 1e-9 && std::abs(hh - h) < std::abs(hb - h))) {
+            best = eff;
+            hb = hh;
+          }
+        }
+        h = hb;
+      }
+    }
+    c->h2s = h;
+    c->nty2s = (p->ny + h - 1) / h;
+    c->s2_xcd = (long long)c->ntx2s * c->nty2s < FUSED_DISPATCH_ORDER_BLOCKS_32;
   }
   c->partials = reinterpret_cast<double*>(c->ws);
   c->red_mid = c->partials + (size_t)L.ntx2 * L.nty2 * NQ;
@@ -824,6 +944,7 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace, c
   // smaller states its arithmetic costs more than the bytes it saves
   c->lo16 = lo16_of(p, L.state_bytes);
   c->d.lo16 = c->lo16 ? 1 : 0;
+  c->d.two_step = c->two_step ? 1 : 0;
   hipError_t e = hipHostMalloc((void**)&c->diag_host, (2 * NQ + 6) * sizeof(double), hipHostMallocDefault);
   if (e != hipSuccess) {
     delete c;
@@ -932,6 +1053,7 @@ int lbm_timing(lbm_ctx* c, int enable) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   for (hipEvent_t e : c->tev) hipEventDestroy(e);
   c->tev.clear();
+  c->tev_steps.clear();
   c->timing = enable != 0;
   return LBM_OK;
 }
@@ -946,7 +1068,9 @@ int lbm_kernel_times(lbm_ctx* c, double* ms_step, int64_t* steps) {
     a += t;
   }
   if (ms_step) *ms_step = a;
-  if (steps) *steps = (int64_t)(c->tev.size() / 2);
+  int64_t ns = 0;
+  for (int k : c->tev_steps) ns += k;
+  if (steps) *steps = ns;
   return LBM_OK;
 }
 
@@ -1054,7 +1178,7 @@ int lbm_snapshot(lbm_ctx* c, void* dst) {
   const size_t nb = c->prec == 64 ? Store<double>::NB : Store<float>::NB;
   char* base = c->state + (size_t)c->cur * nb * pb;
   HIPCHK(c, hipMemcpyAsync(dst, base, nb * pb, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(static_cast<char*>(dst) + nb * pb, c->state + 2 * nb * pb, pb,
+  HIPCHK(c, hipMemcpyAsync(static_cast<char*>(dst) + nb * pb, c->state + (2 * nb + c->scur) * pb, pb,
                            hipMemcpyDeviceToDevice, c->stream));
   return LBM_OK;
 }
@@ -1065,7 +1189,7 @@ int lbm_restore(lbm_ctx* c, const void* src, int64_t step) {
   const size_t nb = c->prec == 64 ? Store<double>::NB : Store<float>::NB;
   char* base = c->state + (size_t)c->cur * nb * pb;
   HIPCHK(c, hipMemcpyAsync(base, src, nb * pb, hipMemcpyDeviceToDevice, c->stream));
-  HIPCHK(c, hipMemcpyAsync(c->state + 2 * nb * pb, static_cast<const char*>(src) + nb * pb, pb,
+  HIPCHK(c, hipMemcpyAsync(c->state + (2 * nb + c->scur) * pb, static_cast<const char*>(src) + nb * pb, pb,
                            hipMemcpyDeviceToDevice, c->stream));
   c->step = step;
   c->nonfinite = false;

@@ -74,7 +74,9 @@ def test_derive_from_sigma_W():
     dict(nx=0), dict(ny=-3), dict(bc_x=2), dict(precision=16), dict(phi_A=-1.0),
     dict(rho_B=0.0), dict(rho_A=-2.0), dict(nu_A=0.0), dict(M=0.0), dict(alpha=0.0),
     dict(kappa=-1.0, beta=0.0), dict(diag_every=-1), dict(nx=65536, ny=65536),
-    dict(gx=float("nan")), dict(kernel_path=3), dict(kernel_path=-1), dict(nu_form=3),
+    dict(gx=float("nan")), dict(kernel_path=3), dict(kernel_path=4), dict(kernel_path=-1),
+    dict(kernel_path=3, precision=32, bc_x=1, bc_y=0), dict(kernel_path=3, precision=32, bc_x=0, bc_y=1),
+    dict(nu_form=3),
     dict(nu_form=-1), dict(collision=2), dict(collision=1, mrt_f=(0.0, 1.0, 1.0, 1.0)),
     dict(collision=1, mrt_g=(1.0, 2.0)), dict(collision=1, mrt_f=(1.0, 1.0, float("nan"), 1.0)),
     dict(lo_format=3), dict(lo_format=-1), dict(use_tau=2),
@@ -84,6 +86,27 @@ def test_derive_rejects(bad):
     rc, _ = _derive(p)
     assert rc == _lib.LBM_EINVAL
     assert _lib.load().lbm_state_bytes(ctypes.byref(p)) == 0
+
+
+def test_two_step_path_is_for_fp32_on_periodic_grids():
+    # kernel_path 3 (two steps per launch) takes FP32 with both directions
+    # periodic; FP64 and walls are rejected above
+    p = make_params(inputs.FLAT, precision=32, kernel_path=3, bc_x=0, bc_y=0)
+    rc, d = _derive(p)
+    assert rc == 0 and d.two_step == 1
+
+
+@pytest.mark.parametrize("over,want", [
+    (dict(precision=32, nx=4096, ny=4096), 1),          # state beyond the last-level cache
+    (dict(precision=32, nx=1024, ny=1024), 0),          # 168 MiB: fits it
+    (dict(precision=64, nx=4096, ny=4096), 0),
+    (dict(precision=32, nx=4096, ny=4096, bc_x=1), 0),
+    (dict(precision=32, nx=4096, ny=4096, kernel_path=2), 0),
+    (dict(precision=32, nx=1024, ny=1024, kernel_path=3), 1),
+])
+def test_automatic_two_step_choice(over, want):
+    rc, d = _derive(make_params(inputs.COALESCENCE, **over))
+    assert rc == 0 and d.two_step == want
 
 
 def test_derive_from_relaxation_times():
@@ -132,8 +155,8 @@ def test_state_bytes(prec, esz):
     p = make_params(inputs.FLAT, precision=prec)
     nb = _lib.load().lbm_state_bytes(ctypes.byref(p))
     # two population buffers (18 planes in FP64, 19 in FP32: f_0 as hi + lo),
-    # plus S, phi, mu, each plane at least nx*ny cells
-    planes = 39 if prec == 64 else 41
+    # plus two S planes, phi, mu, each plane at least nx*ny cells
+    planes = 40 if prec == 64 else 42
     assert nb >= planes * 256 * 4 * esz and nb % 256 == 0
     big = make_params(inputs.THROUGHPUT, precision=prec)
     nbb = _lib.load().lbm_state_bytes(ctypes.byref(big))
