@@ -142,27 +142,31 @@ __device__ __forceinline__ A d2psi_b(const KP& p, A ph) {
 }
 
 // Sum-reduce NV values over the block and add them to out[0..NV) (the
-// block owns `out`; launches on one stream never overlap).
-template <int NV>
+// block owns `out`; launches on one stream never overlap).  The block's sum
+// is taken in A: the FP32 adjoint kernels sum their FP32 per-cell terms in
+// FP32 (a wave butterfly of one word per step instead of two), and the
+// per-tile partials they add to stay FP64 across the steps.
+template <int NV, typename A = double>
 __device__ __forceinline__ void block_sum_add(double (&v)[NV], double* __restrict__ out) {
-  __shared__ double red[16][NV];
+  __shared__ A red[16][NV];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  A s[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
-    double a = v[k];
+    A a = (A)v[k];
 #pragma unroll
-    for (int s = 32; s >= 1; s >>= 1) a += __shfl_xor(a, s, 64);
-    v[k] = a;
+    for (int d = 32; d >= 1; d >>= 1) a += __shfl_xor(a, d, 64);
+    s[k] = a;
   }
   if (lane == 0)
-    for (int k = 0; k < NV; ++k) red[wave][k] = v[k];
+    for (int k = 0; k < NV; ++k) red[wave][k] = s[k];
   __syncthreads();
   if (threadIdx.x == 0) {
     const int nw = blockDim.x >> 6;
     for (int k = 0; k < NV; ++k) {
-      double a = red[0][k];
+      A a = red[0][k];
       for (int w = 1; w < nw; ++w) a += red[w][k];
-      out[k] += a;
+      out[k] += (double)a;
     }
   }
 }
@@ -188,10 +192,19 @@ struct KaCell {
   T lphi, lmu, lgpx, lgpy, lgmx, lgmy;
 };
 
-template <typename T, bool INIT, bool MRT = false>
+// Periodic grids (PER): the cell's row y is the same on a whole wave, so
+// every access is a scalar base (plane and row, y - 1, y or y + 1 wrapped)
+// plus one of three per-lane byte offsets (columns x - 1, x, x + 1 wrapped);
+// no wall selects.
+struct PerCols {
+  unsigned bm, bc, bp;  // 4 * column of x - 1, x, x + 1
+  int ym, yp;           // rows y - 1, y + 1
+};
+
+template <typename T, bool INIT, bool MRT = false, bool PER = false>
 __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, const T* __restrict__ dphi,
                                         const T* __restrict__ mupl, const T* __restrict__ lam_in, int x,
-                                        int y, KaCell<T>& o, double (&th)[4]) {
+                                        int y, KaCell<T>& o, double (&th)[4], const PerCols& pc = PerCols{}) {
   // The adjoint owes no bitwise match to anything: let a * b + c contract.
 #pragma clang fp contract(fast)
   using C = T;
@@ -205,9 +218,30 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   // (1024^2 FP32: 0.1109 against 0.1124 ms per adjoint step incl. recompute).
   constexpr bool F0 = !std::is_same<T, float>::value;
   Pops<T> q;
-  gather<true, T, true, F0, false, true>(B, p, x, y, q);
   Nbhd<T> nb;
-  load_nbhd(p, dphi, mupl, x, y, nb);
+  if constexpr (PER) {
+    // pull sources x - c_i; the stencils' neighbours x + (dx, dy)
+    auto col = [&](int cx) { return cx == 1 ? pc.bm : (cx == -1 ? pc.bp : pc.bc); };
+    auto row = [&](int cy) { return cy == 1 ? pc.ym : (cy == -1 ? pc.yp : y); };
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      const long long r = (long long)row(cy_of(i)) * p.pitch;
+      if (F0 || i != 0) q.f[i] = ld_nt_at(B + i * p.ps + r, col(cx_of(i)));
+      q.g[i] = ld_nt_at(B + (9 + i) * p.ps + r, col(cx_of(i)));
+    }
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const long long r = (long long)row(1 - a) * p.pitch;  // a = 0: y - 1
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        nb.ph[a][b] = ld_at(dphi + r, col(1 - b));  // b = 0: x - 1
+        nb.mu[a][b] = ld_at(mupl + r, col(1 - b));
+      }
+    }
+  } else {
+    gather<true, T, true, F0, false, true>(B, p, x, y, q);
+    load_nbhd(p, dphi, mupl, x, y, nb);
+  }
   const C phi_ref = C(p.phi_ref);
   C ph3[3][3];
 #pragma unroll
@@ -237,11 +271,11 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   const C rho = C(p.rhoB) + dB * rs;
   const C nu = visc<C>(p, dB);
   const C tau = half + three * nu;
-  const C wg = one / tau, kG = one - half * wg;
+  const C wg = recip(tau), kG = one - half * wg;
   const C Fx = C(p.gx) - phi * gmx, Fy = C(p.gy) - phi * gmy;
   const C mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
   const C my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
-  const C irho = one / rho;
+  const C irho = recip(rho);
   const C ux = (mx + half * Fx) * irho, uy = (my + half * Fy) * irho;
   const C uu = ux * ux + uy * uy;
   const C snz = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
@@ -255,6 +289,16 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   if (INIT) {
 #pragma unroll
     for (int i = 0; i < 9; ++i) a[i] = c[i] = C(0);
+  } else if constexpr (PER) {
+    // P^T on a periodic grid: lambda_{f*_j}(x) = lambda'_j(x + c_j)
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+      const int cx = cx_of(j), cy = cy_of(j);
+      const unsigned cb = cx == 1 ? pc.bp : (cx == -1 ? pc.bm : pc.bc);
+      const long long r = (long long)(cy == 1 ? pc.yp : (cy == -1 ? pc.ym : y)) * p.nx;
+      a[j] = ld_at(lam_in + j * n + r, cb);
+      c[j] = ld_at(lam_in + (9 + j) * n + r, cb);
+    }
   } else {
     // P^T: lambda_{f*_j}(x) = lambda'_j(x + c_j) if that link is fluid,
     // else lambda'_opp(j)(x) (the bounce-back image).
@@ -271,7 +315,10 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
       c[j] = lc[k];
     }
   }
-  lS = uni(lam_in + 18 * n)[kd];  // S_prev(n+1) = S(n): no streaming
+  if constexpr (PER)
+    lS = ld_at(lam_in + 18 * n + (long long)y * p.nx, pc.bc);
+  else
+    lS = uni(lam_in + 18 * n)[kd];  // S_prev(n+1) = S(n): no streaming
 
   // ---- order-parameter collision: f* = f - w_f (f - f^eq) + w b (3/2 S - 1/2 S_prev)
   // (MRT: f* = f + R_f (f^eq - f) + ..., R = M^-1 S M, which is symmetric for
@@ -454,7 +501,7 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   o.lgmy = lgmy;
 }
 
-template <typename T, bool INIT, bool MRT = false>
+template <typename T, bool INIT, bool MRT = false, bool PER = false>
 __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict__ B,
                                                  const T* __restrict__ dphi,
                                                  const T* __restrict__ mupl,
@@ -463,24 +510,45 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
                                                  int ntx) {
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int x = (tile % ntx) * K2_TX + (threadIdx.x & (K2_TX - 1));
-  const int y = (tile / ntx) * K2_TY + threadIdx.x / K2_TX;
+  // a tile row is one wave (K2_TX = 64): y is uniform over the wave
+  const int y = (tile / ntx) * K2_TY + __builtin_amdgcn_readfirstlane(threadIdx.x / K2_TX);
   double th[4] = {0.0, 0.0, 0.0, 0.0};  // alpha, tau_f, nu_A, nu_B
   if (x < p.nx && y < p.ny) {
     const long long n = (long long)p.nx * p.ny;
     const unsigned kd = (unsigned)(y * p.nx + x);
     KaCell<T> o;
-    ka_cell<T, INIT, MRT>(p, B, dphi, mupl, lam_in, x, y, o, th);
+    if constexpr (PER) {
+      PerCols pc;
+      pc.bm = (unsigned)((x > 0 ? x - 1 : p.nx - 1) * sizeof(T));
+      pc.bp = (unsigned)((x < p.nx - 1 ? x + 1 : 0) * sizeof(T));
+      pc.bc = (unsigned)(x * sizeof(T));
+      pc.ym = y > 0 ? y - 1 : p.ny - 1;
+      pc.yp = y < p.ny - 1 ? y + 1 : 0;
+      ka_cell<T, INIT, MRT, true>(p, B, dphi, mupl, lam_in, x, y, o, th, pc);
+      const long long r = (long long)y * p.nx;
 #pragma unroll
-    for (int i = 0; i < 9; ++i) uni(lam_out + (9 + i) * n)[kd] = o.lg[i];
-    uni(lam_out + 18 * n)[kd] = o.lS;
-    uni(w.lphi)[kd] = o.lphi;
-    uni(w.lmu)[kd] = o.lmu;
-    uni(w.lgpx)[kd] = o.lgpx;
-    uni(w.lgpy)[kd] = o.lgpy;
-    uni(w.lgmx)[kd] = o.lgmx;
-    uni(w.lgmy)[kd] = o.lgmy;
+      for (int i = 0; i < 9; ++i) st_at<false>(lam_out + (9 + i) * n + r, pc.bc, o.lg[i]);
+      st_at<false>(lam_out + 18 * n + r, pc.bc, o.lS);
+      st_at<false>(w.lphi + r, pc.bc, o.lphi);
+      st_at<false>(w.lmu + r, pc.bc, o.lmu);
+      st_at<false>(w.lgpx + r, pc.bc, o.lgpx);
+      st_at<false>(w.lgpy + r, pc.bc, o.lgpy);
+      st_at<false>(w.lgmx + r, pc.bc, o.lgmx);
+      st_at<false>(w.lgmy + r, pc.bc, o.lgmy);
+    } else {
+      ka_cell<T, INIT, MRT>(p, B, dphi, mupl, lam_in, x, y, o, th);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) uni(lam_out + (9 + i) * n)[kd] = o.lg[i];
+      uni(lam_out + 18 * n)[kd] = o.lS;
+      uni(w.lphi)[kd] = o.lphi;
+      uni(w.lmu)[kd] = o.lmu;
+      uni(w.lgpx)[kd] = o.lgpx;
+      uni(w.lgpy)[kd] = o.lgpy;
+      uni(w.lgmx)[kd] = o.lgmx;
+      uni(w.lgmy)[kd] = o.lgmy;
+    }
   }
-  block_sum_add<4>(th, th_part + (long long)tile * NTH + 2);
+  block_sum_add<4, T>(th, th_part + (long long)tile * NTH + 2);
 }
 
 // ------------------------------------------------------------- KA2 + KA3
@@ -535,10 +603,14 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
       const int k = min((int)threadIdx.x + e * KM_THREADS, LH * LW - 1);
       const int ly = k / LW, lx = k - ly * LW;
       const int gx = stencil_idx(x0 + lx - 1, p.nx, 0), gy = stencil_idx(y0 + ly - 1, p.ny, 0);
-      lm[e] = w.lmu[(unsigned)(gy * p.nx + gx)];
+      // the preimages gx - c_x, gy - c_y: three columns and three rows
+      const unsigned cx3[3] = {(unsigned)pre1(gx, 1, p.nx), (unsigned)gx, (unsigned)pre1(gx, -1, p.nx)};
+      const unsigned ry3[3] = {(unsigned)(pre1(gy, 1, p.ny) * p.nx), (unsigned)(gy * p.nx),
+                               (unsigned)(pre1(gy, -1, p.ny) * p.nx)};
+      lm[e] = w.lmu[ry3[1] + cx3[1]];
 #pragma unroll
       for (int d = 1; d < 9; ++d) {
-        const unsigned kk = (unsigned)(pre1(gy, cy_of(d), p.ny) * p.nx + pre1(gx, cx_of(d), p.nx));
+        const unsigned kk = ry3[1 - cy_of(d)] + cx3[1 - cx_of(d)];
         gxv[e][d - 1] = cx_of(d) != 0 ? w.lgmx[kk] : C(0);
         gyv[e][d - 1] = cy_of(d) != 0 ? w.lgmy[kk] : C(0);
       }
@@ -590,37 +662,37 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
       C gpx[8], gpy[8];    // lambda_{grad phi} at the preimages (G^T)
       C a[9];              // lambda_{f*}: the transposed pull of lam_in
     };
+    // A thread keeps its column (x, clamped on ragged tiles: columns and
+    // rows beyond the grid load a valid cell and are not stored) and takes
+    // rows that are the same on its whole wave: every access is a scalar
+    // base (plane and row) plus one of three per-lane byte offsets.
+    const int xc = min(x, p.nx - 1);
+    const unsigned cb[3] = {(unsigned)(pre1(xc, 1, p.nx) * sizeof(C)), (unsigned)(xc * sizeof(C)),
+                            (unsigned)(pre1(xc, -1, p.nx) * sizeof(C))};  // x - 1, x, x + 1
     auto load_row = [&](int ty, RowIn& in) {
-      // rows and columns beyond the grid (ragged tiles) load a valid cell
-      // and are not stored
-      const int y = min(y0 + ty, p.ny - 1), xc = min(x, p.nx - 1);
-      const int xs[3] = {stencil_idx(xc - 1, p.nx, 0), xc, stencil_idx(xc + 1, p.nx, 0)};
-      const int ys[3] = {stencil_idx(y - 1, p.ny, 0), y, stencil_idx(y + 1, p.ny, 0)};
+      const int y = min(y0 + ty, p.ny - 1);
+      const int ys[3] = {pre1(y, 1, p.ny), y, pre1(y, -1, p.ny)};  // y - 1, y, y + 1
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
-        for (int b = 0; b < 3; ++b) in.v[a][b] = dphi[(unsigned)(ys[a] * p.pitch + xs[b])];
-      const unsigned kd = (unsigned)(y * p.nx + xc);
-      in.lphi = w.lphi[kd];
+        for (int b = 0; b < 3; ++b) in.v[a][b] = ld_at(dphi + (long long)ys[a] * p.pitch, cb[b]);
+      in.lphi = ld_at(w.lphi + (long long)y * p.nx, cb[1]);
 #pragma unroll
-      for (int d = 1; d < 9; ++d) {
-        const unsigned kk = (unsigned)(pre1(y, cy_of(d), p.ny) * p.nx + pre1(xc, cx_of(d), p.nx));
-        in.gpx[d - 1] = cx_of(d) != 0 ? w.lgpx[kk] : C(0);
-        in.gpy[d - 1] = cy_of(d) != 0 ? w.lgpy[kk] : C(0);
+      for (int d = 1; d < 9; ++d) {  // preimage x - c_d
+        const long long r = (long long)ys[1 - cy_of(d)] * p.nx;
+        in.gpx[d - 1] = cx_of(d) != 0 ? ld_at(w.lgpx + r, cb[1 - cx_of(d)]) : C(0);
+        in.gpy[d - 1] = cy_of(d) != 0 ? ld_at(w.lgpy + r, cb[1 - cx_of(d)]) : C(0);
       }
 #pragma unroll
-      for (int j = 0; j < 9; ++j) {
+      for (int j = 0; j < 9; ++j) {  // transposed pull: x + c_j
         in.a[j] = C(0);
-        if (!INIT) {
-          const int qx = pre1(xc, -cx_of(j), p.nx), qy = pre1(y, -cy_of(j), p.ny);
-          in.a[j] = uni(lam_in + j * n)[(unsigned)(qy * p.nx + qx)];
-        }
+        if (!INIT) in.a[j] = ld_at(lam_in + j * n + (long long)ys[1 + cy_of(j)] * p.nx, cb[1 + cx_of(j)]);
       }
     };
     auto finish_row = [&](int ty, RowIn& in) {
       const int y = y0 + ty;
       if (x >= p.nx || y >= p.ny) return;
-      const unsigned kd = (unsigned)(y * p.nx + x);
+      const long long ry = (long long)y * p.nx;
       const int lx = tx + 1, ly = ty + 1;
       const C lmt = mt[ly][lx];
       C lt = C(0);
@@ -648,14 +720,15 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
         mrt_rates_f(p, C(p.omega_f), rate);
         mrt_relax<C, false>(rate, in.a, in.a, ra);
 #pragma unroll
-        for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = (in.a[j] - ra[j]) + lphi;
+        for (int j = 0; j < 9; ++j) st_at<false>(lam_out + j * n + ry, cb[1], (in.a[j] - ra[j]) + lphi);
       } else {
 #pragma unroll
-        for (int j = 0; j < 9; ++j) uni(lam_out + j * n)[kd] = k1 * in.a[j] + lphi;
+        for (int j = 0; j < 9; ++j) st_at<false>(lam_out + j * n + ry, cb[1], k1 * in.a[j] + lphi);
       }
     };
     constexpr int NR = KM_TY / (KM_THREADS / KM_TX);  // rows per thread
-    const int ty0 = threadIdx.x / KM_TX;
+    // a tile row is one wave (KM_TX = 64)
+    const int ty0 = __builtin_amdgcn_readfirstlane(threadIdx.x / KM_TX);
     RowIn in[2];
     load_row(ty0, in[0]);
 #pragma unroll
@@ -726,7 +799,7 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
       }
     }
   }
-  block_sum_add<2>(th, th_part + (long long)tile * NTH + 0);
+  block_sum_add<2, T>(th, th_part + (long long)tile * NTH + 0);
 }
 
 // ---------------------------------------------------- initialisation adjoint

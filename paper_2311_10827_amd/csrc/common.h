@@ -270,6 +270,31 @@ __device__ __forceinline__ gmem<P> uni(P* ptr) {
   return (gmem<P>)(((unsigned long long)hi << 32) | lo);
 }
 
+// Global load and store at a wave-uniform base plus a per-lane byte offset
+// (one vector register; the base stays in scalar registers).
+template <typename P>
+__device__ __forceinline__ P ld_at(const P* base, unsigned byte_off) {
+  using G = __attribute__((address_space(1))) const char*;
+  const G b = (G)uni(base);
+  return *(__attribute__((address_space(1))) const P*)(b + byte_off);
+}
+template <typename P>
+__device__ __forceinline__ P ld_nt_at(const P* base, unsigned byte_off) {
+  using G = __attribute__((address_space(1))) const char*;
+  const G b = (G)uni(base);
+  return __builtin_nontemporal_load((__attribute__((address_space(1))) const P*)(b + byte_off));
+}
+template <bool NT, typename P>
+__device__ __forceinline__ void st_at(P* base, unsigned byte_off, P v) {
+  using G = __attribute__((address_space(1))) char*;
+  const G b = (G)uni(base);
+  __attribute__((address_space(1))) P* ptr = (__attribute__((address_space(1))) P*)(b + byte_off);
+  if constexpr (NT)
+    __builtin_nontemporal_store(v, ptr);
+  else
+    *ptr = v;
+}
+
 // Stencil neighbour: periodic wrap, or the mirrored adjacent cell across a
 // wall.  Valid for any integer v; one period out of range costs a compare,
 // the general remainder runs only for lanes farther out.
@@ -322,6 +347,15 @@ __device__ __forceinline__ const short* lo_plane(const T* B, const KP& p) {
 template <typename T>
 __device__ __forceinline__ short* lo_plane(T* B, const KP& p) {
   return reinterpret_cast<short*>(B + LO_PLANE * p.ps);
+}
+
+// 1/x: in FP32 the hardware reciprocal (1 ulp), in FP64 the division.
+template <typename C>
+__device__ __forceinline__ C recip(C x) {
+  if constexpr (std::is_same<C, float>::value)
+    return __builtin_amdgcn_rcpf(x);
+  else
+    return C(1) / x;
 }
 
 // A load, streaming (non-temporal) when NTL.

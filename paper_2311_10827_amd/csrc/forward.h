@@ -301,7 +301,7 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
   const float mx = ((g[1] - g[3]) + (g[5] - g[7])) + (g[8] - g[6]);
   const float my = ((g[2] - g[4]) + (g[5] - g[7])) + (g[6] - g[8]);
   const float gnz = ((g[1] + g[2]) + (g[3] + g[4])) + ((g[5] + g[6]) + (g[7] + g[8]));
-  const float irho = __builtin_amdgcn_rcpf(rho);  // the hardware reciprocal (1 ulp)
+  const float irho = recip(rho);  // the hardware reciprocal (1 ulp)
   const float ux = (mx + 0.5f * Fx) * irho, uy = (my + 0.5f * Fy) * irho;
   const float uu = ux * ux + uy * uy;
   const float ugr = ux * grx + uy * gry;
@@ -346,7 +346,7 @@ __device__ __forceinline__ void cell_f32(const KP& p, const Pops<float>& q, cons
     if constexpr (MRT) fo[i] += corr_f[i];
   }
   const float tau = 0.5f + 3.0f * visc<float>(p, dB);
-  const float wg = __builtin_amdgcn_rcpf(tau);
+  const float wg = recip(tau);
   const float kG = 1.0f - 0.5f * wg;
   const float ge0 = -(float)(5.0 / 3.0) * pr - (float)(2.0 / 3.0) * rho * uu;
   go[0] = g[0] + wg * (ge0 - g[0]);

@@ -686,15 +686,25 @@ int adjoint_step_impl(lbm_ctx* c, T* state, const T* lam_in, T* lam_out, bool ha
   }
   const unsigned nb = (unsigned)(c->ntx2 * c->nty2);
   const AdjWork<T> w = adj_work<T>(c);
+  // periodic grids: ka_local's wall-free form (scalar row bases)
+  const bool per = !c->kp.bcx && !c->kp.bcy;
   if (c->kp.collision == LBM_MRT) {
-    hipLaunchKernelGGL((ka_local<T, false, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu,
-                       lam_in, lam_out, w, c->th_part, c->ntx2);
+    if (per)
+      hipLaunchKernelGGL((ka_local<T, false, true, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi,
+                         mu, lam_in, lam_out, w, c->th_part, c->ntx2);
+    else
+      hipLaunchKernelGGL((ka_local<T, false, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu,
+                         lam_in, lam_out, w, c->th_part, c->ntx2);
     LAUNCHCHK(c);
     hipLaunchKernelGGL((ka_mu_phi<T, false, true>), dim3(c->ntxm * c->ntym), dim3(KM_THREADS), 0, c->stream,
                        c->kp, dphi, lam_in, lam_out, w, c->th_part, c->ntxm);
   } else {
-    hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu,
-                       lam_in, lam_out, w, c->th_part, c->ntx2);
+    if (per)
+      hipLaunchKernelGGL((ka_local<T, false, false, true>), dim3(nb), dim3(256), 0, c->stream, c->kp, state,
+                         dphi, mu, lam_in, lam_out, w, c->th_part, c->ntx2);
+    else
+      hipLaunchKernelGGL((ka_local<T, false>), dim3(nb), dim3(256), 0, c->stream, c->kp, state, dphi, mu,
+                         lam_in, lam_out, w, c->th_part, c->ntx2);
     LAUNCHCHK(c);
     hipLaunchKernelGGL((ka_mu_phi<T, false>), dim3(c->ntxm * c->ntym), dim3(KM_THREADS), 0, c->stream,
                        c->kp, dphi, lam_in, lam_out, w, c->th_part, c->ntxm);

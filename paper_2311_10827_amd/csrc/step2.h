@@ -31,25 +31,6 @@ constexpr int S2_L = 256;  // lanes per workgroup
 constexpr int S2_WMAX = S2_L - 10;  // widest strip: step A's phi takes W + 10 lanes
 constexpr int S2_H = 128;  // tallest strip; the host may lower it
 
-// Global load and store at a wave-uniform base plus a per-lane byte offset
-// (one vector register; the base stays in scalar registers).
-template <typename P>
-__device__ __forceinline__ P ld_at(const P* base, unsigned byte_off) {
-  using G = __attribute__((address_space(1))) const char*;
-  const G b = (G)uni(base);
-  return *(__attribute__((address_space(1))) const P*)(b + byte_off);
-}
-template <bool NT, typename P>
-__device__ __forceinline__ void st_at(P* base, unsigned byte_off, P v) {
-  using G = __attribute__((address_space(1))) char*;
-  const G b = (G)uni(base);
-  __attribute__((address_space(1))) P* ptr = (__attribute__((address_space(1))) P*)(b + byte_off);
-  if constexpr (NT)
-    __builtin_nontemporal_store(v, ptr);
-  else
-    *ptr = v;
-}
-
 __device__ __forceinline__ int wrap_row(int v, int n) { return stencil_idx(v, n, 0); }
 
 // Directions by the row they are pulled from: cy = -1 (4 S, 7 SW, 8 SE) from
