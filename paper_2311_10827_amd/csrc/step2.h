@@ -19,7 +19,8 @@
 // the lane that computed them; each row, every lane stages the few values
 // the pull gathers of step B read from its neighbours into LDS (f for B's phi
 // of one row, g for B's collision of another), so no full intermediate row
-// of 19 planes is held anywhere.  S (u . grad phi) of step n + 2 goes to a
+// of 19 planes is held anywhere.  Step A's own gathered f waits in an LDS
+// ring of three rows between its phi and its collision.  S (u . grad phi) of step n + 2 goes to a
 // second S plane: step A needs S_prev of step n on the halo cells, which the
 // strips beside it would otherwise overwrite.
 #pragma once
@@ -53,6 +54,7 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
   __shared__ float muB[3][S2_L];
   __shared__ float SF[10][S2_L];   // A's f_0..f_8 and low word, for B's phi gather
   __shared__ float SG[2][9][S2_L]; // A's g, for B's collision gather (two rows in turn)
+  __shared__ float FA[3][10][S2_L]; // step A's gathered f of rows k, k+1, k+2 (by row mod 3)
 
   const int blk = xcd_order ? xcd_tile(blockIdx.x, gridDim.x) : (int)blockIdx.x;
   const int x0 = (blk % ntx) * W, y0 = (blk / ntx) * H;
@@ -67,6 +69,14 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
   const bool rColB = l >= 5 && l < W + 5 && cu < p.nx;
   const long long ps = p.ps;
   const int pitch = p.pitch;
+  // the buffers, made opaque once per row below: the compiler then forms
+  // each plane's base next to its access (scalar arithmetic) instead of
+  // keeping some forty 64-bit plane bases live across the loop, which it
+  // cannot hold in scalar registers without spilling them
+  const float* Bi = Bin;
+  float* Bo = Bout;
+  const float* Si = Sin;
+  float* So = Sout;
 
   // byte offset of the pull source column of direction i
   auto colb = [&](int i) { return cx_of(i) == 1 ? bxm : (cx_of(i) == -1 ? bxp : bxc); };
@@ -76,21 +86,21 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int sy = cy_of(i) == 1 ? ym : (cy_of(i) == -1 ? yp : yc);
-      f[i] = ld_at(Bin + i * ps + (long long)sy * pitch, colb(i));
+      f[i] = ld_at(Bi + i * ps + (long long)sy * pitch, colb(i));
     }
     if constexpr (LO16)
-      f[9] = lo_decode(f[0], ld_at(lo_plane(Bin, p) + (long long)yc * pitch, bxc >> 1));
+      f[9] = lo_decode(f[0], ld_at(lo_plane(Bi, p) + (long long)yc * pitch, bxc >> 1));
     else
-      f[9] = ld_at(Bin + LO_PLANE * ps + (long long)yc * pitch, bxc);
+      f[9] = ld_at(Bi + LO_PLANE * ps + (long long)yc * pitch, bxc);
   };
   auto gather_g = [&](int r, float (&g)[9], float& Sp) {
     const int ym = wrap_row(r - 1, p.ny), yc = wrap_row(r, p.ny), yp = wrap_row(r + 1, p.ny);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const int sy = cy_of(i) == 1 ? ym : (cy_of(i) == -1 ? yp : yc);
-      g[i] = ld_at(Bin + (9 + i) * ps + (long long)sy * pitch, colb(i));
+      g[i] = ld_at(Bi + (9 + i) * ps + (long long)sy * pitch, colb(i));
     }
-    Sp = ld_at(Sin + (long long)yc * pitch, bxc);
+    Sp = ld_at(Si + (long long)yc * pitch, bxc);
   };
   auto phi_of = [&](const float (&f)[10]) {
     Pops<float> q;
@@ -120,9 +130,8 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
     }
   };
 
-  // Step A's gathered f of rows k, k+1 (k+2 arrives in the iteration);
-  // step B's gathered f of rows k-4, k-3 (k-2 arrives).
-  float fa0[10], fa1[10], fb0[10], fb1[10];
+  // step B's gathered f of rows k-4, k-3 (k-2 arrives in the iteration)
+  float fb0[10], fb1[10];
   // Step A's output by age (rows k-1, k-2, ... at the top of iteration k):
   // f at ages 1-3, g at ages 1-5, S at ages 1-4.  Ages past a value's last
   // use are not kept (f: age 2 keeps cy >= 0, age 3 cy = +1; g: age 4 keeps
@@ -145,13 +154,9 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
       gather_f(r, f);
       phA[mod_pos(r, 5)][l] = phi_of(f);
     }
-    if (r == y0 - 3) {
+    if (r >= y0 - 3 && rColA) {
 #pragma unroll
-      for (int i = 0; i < 10; ++i) fa0[i] = f[i];
-    }
-    if (r == y0 - 2) {
-#pragma unroll
-      for (int i = 0; i < 10; ++i) fa1[i] = f[i];
+      for (int i = 0; i < 10; ++i) FA[mod_pos(r, 3)][i][l] = f[i];
     }
   }
   __syncthreads();
@@ -171,13 +176,15 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
     // its access (the scalar-base form of the global access) instead of
     // adding 64-bit vector sums hoisted out of the loop.
     asm volatile("" : "+v"(bxc), "+v"(bxm), "+v"(bxp));
+    asm volatile("" : "+s"(Bi), "+s"(Bo), "+s"(Si), "+s"(So));
     const bool doA = k <= y1 + 2;
     // ---- P1: phi_A(k+2); stage A's output for B
-    float fa2[10];
     if (doA && rPhiA) {
       phA[mod_pos(k + 2, 5)][l] = phi_of(fN);
+      if (rColA) {
 #pragma unroll
-      for (int i = 0; i < 10; ++i) fa2[i] = fN[i];
+        for (int i = 0; i < 10; ++i) FA[mod_pos(k + 2, 3)][i][l] = fN[i];
+      }
       // the next row's f goes out at once: a whole iteration hides it
       if (k + 1 <= y1 + 2) gather_f(k + 3, fN);
     }
@@ -221,12 +228,13 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
     float nS = 0.f;
     if (doA && rColA) {
       Pops<float> q;
+      const float(*fk)[S2_L] = FA[mod_pos(k, 3)];
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        q.f[i] = fa0[i];
+        q.f[i] = fk[i][l];
         q.g[i] = gN[i];
       }
-      q.lo = fa0[9];
+      q.lo = fk[9][l];
       Nbhd<float> nb;
       nbhd_at(phA, muA, k, nb);
       CellOut c;
@@ -260,20 +268,18 @@ __global__ __launch_bounds__(S2_L, 2) void k_step2(const KP p, const float* Bin,
       const long long row = (long long)y * pitch;
 #pragma unroll
       for (int i = 0; i < 9; ++i) {
-        st_at<NT>(Bout + i * ps + row, bxc, fo[i]);
-        st_at<NT>(Bout + (9 + i) * ps + row, bxc, go[i]);
+        st_at<NT>(Bo + i * ps + row, bxc, fo[i]);
+        st_at<NT>(Bo + (9 + i) * ps + row, bxc, go[i]);
       }
       if constexpr (LO16)
-        st_at<NT>(lo_plane(Bout, p) + row, bxc >> 1, lo_encode(fo[0], lo));
+        st_at<NT>(lo_plane(Bo, p) + row, bxc >> 1, lo_encode(fo[0], lo));
       else
-        st_at<NT>(Bout + LO_PLANE * ps + row, bxc, lo);
-      st_at<NT>(Sout + row, bxc, (float)c.S);
+        st_at<NT>(Bo + LO_PLANE * ps + row, bxc, lo);
+      st_at<NT>(So + row, bxc, (float)c.S);
     }
     // ---- the rings and S age by one row
 #pragma unroll
     for (int i = 0; i < 10; ++i) {
-      fa0[i] = fa1[i];
-      fa1[i] = fa2[i];
       fb0[i] = fb1[i];
       fb1[i] = fb2[i];
     }
