@@ -305,9 +305,11 @@ def coalescence_leg(dev, steps: int, warmup: int):
 def adjoint_leg(nsteps: int, K: int, n: int = 0):
     """Inverse-problem gradient on the 1024^2 two-drop workload (FP32): the
     adjoint step's cost, including its share of the checkpoint recompute,
-    relative to a forward step on the faster of the two step forms at this
-    size (the forward state fits in the GPU's caches here).  n > 0: the same
-    workload on an n x n grid, drop radius scaled with it."""
+    relative to a forward step on the fastest of the library's step forms at
+    this size (fused, two-kernel, two steps per launch; at 1024^2 the
+    forward state fits in the GPU's caches and the fused step is the
+    fastest).  n > 0: the same workload on an n x n grid, drop radius scaled
+    with it."""
     import dataclasses
 
     import torch
@@ -330,12 +332,12 @@ def adjoint_leg(nsteps: int, K: int, n: int = 0):
     hidden[2] *= s2          # M scaled by s2
     log(f"[bench] adjoint: target with hidden (sigma, M) x ({s1:.3f}, {s2:.3f})")
     tgt = Sim(params_from_theta(base, hidden), phi0).step(nsteps).moments(diag=False)["phi"]
-    # forward step time of the same workload on both step forms; the faster
-    # one is the reference.  The rollout (and so its checkpoint recompute,
-    # which writes every state to a snapshot of its own) runs the fused
-    # kernel, which writes fewer bytes per recomputed state.
+    # forward step time of the same workload on every step form; the fastest
+    # is the reference.  The rollout (and so its checkpoint recompute, which
+    # writes every state to a snapshot of its own) runs the fused kernel,
+    # which writes fewer bytes per recomputed state.
     t_fwd = {}
-    for kp in (2, 1):
+    for kp in (2, 1, 3):
         base.kernel_path = kp
         sim = Sim(params_from_theta(base, theta), phi0)
         sim.step(20)
@@ -350,7 +352,8 @@ def adjoint_leg(nsteps: int, K: int, n: int = 0):
         del sim
     kp_best = min(t_fwd, key=t_fwd.get)
     base.kernel_path = 2
-    log(f"[bench] adjoint: forward ms/step fused {t_fwd[2]:.4f}, two-kernel {t_fwd[1]:.4f}")
+    log(f"[bench] adjoint: forward ms/step fused {t_fwd[2]:.4f}, two-kernel {t_fwd[1]:.4f}, "
+        f"two steps per launch {t_fwd[3]:.4f}")
     log(f"[bench] adjoint: rollout {nsteps} steps, checkpoint every {K} (one warm-up gradient, "
         "then the timed one: buffers come from torch's caching allocator)")
     for _ in range(2):
@@ -366,7 +369,8 @@ def adjoint_leg(nsteps: int, K: int, n: int = 0):
         "forward_ms_per_step": round(t_fwd[kp_best], 5),
         "forward_ms_per_step_fused": round(t_fwd[2], 5),
         "forward_ms_per_step_two_kernel": round(t_fwd[1], 5),
-        "forward_reference": "fused" if kp_best == 2 else "two-kernel",
+        "forward_ms_per_step_two_step": round(t_fwd[3], 5),
+        "forward_reference": {2: "fused", 1: "two-kernel", 3: "two steps per launch"}[kp_best],
         "rollout_step_form": "fused",
         "adjoint_ms_per_step_incl_recompute": round(t_bwd, 5),
         "ratio": round(t_bwd / t_fwd[kp_best], 3),

@@ -219,10 +219,12 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
   constexpr bool F0 = !std::is_same<T, float>::value;
   Pops<T> q;
   Nbhd<T> nb;
+  // the cell's row, the same on the whole wave (PER)
+  const int yr = PER ? __builtin_amdgcn_readfirstlane(y) : y;
   if constexpr (PER) {
     // pull sources x - c_i; the stencils' neighbours x + (dx, dy)
     auto col = [&](int cx) { return cx == 1 ? pc.bm : (cx == -1 ? pc.bp : pc.bc); };
-    auto row = [&](int cy) { return cy == 1 ? pc.ym : (cy == -1 ? pc.yp : y); };
+    auto row = [&](int cy) { return cy == 1 ? pc.ym : (cy == -1 ? pc.yp : yr); };
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       const long long r = (long long)row(cy_of(i)) * p.pitch;
@@ -295,7 +297,7 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
     for (int j = 0; j < 9; ++j) {
       const int cx = cx_of(j), cy = cy_of(j);
       const unsigned cb = cx == 1 ? pc.bp : (cx == -1 ? pc.bm : pc.bc);
-      const long long r = (long long)(cy == 1 ? pc.yp : (cy == -1 ? pc.ym : y)) * p.nx;
+      const long long r = (long long)(cy == 1 ? pc.yp : (cy == -1 ? pc.ym : yr)) * p.nx;
       a[j] = ld_at(lam_in + j * n + r, cb);
       c[j] = ld_at(lam_in + (9 + j) * n + r, cb);
     }
@@ -316,7 +318,7 @@ __device__ __forceinline__ void ka_cell(const KP& p, const T* __restrict__ B, co
     }
   }
   if constexpr (PER)
-    lS = ld_at(lam_in + 18 * n + (long long)y * p.nx, pc.bc);
+    lS = ld_at(lam_in + 18 * n + (long long)yr * p.nx, pc.bc);
   else
     lS = uni(lam_in + 18 * n)[kd];  // S_prev(n+1) = S(n): no streaming
 
@@ -522,10 +524,12 @@ __global__ __launch_bounds__(256) void ka_local(const KP p, const T* __restrict_
       pc.bm = (unsigned)((x > 0 ? x - 1 : p.nx - 1) * sizeof(T));
       pc.bp = (unsigned)((x < p.nx - 1 ? x + 1 : 0) * sizeof(T));
       pc.bc = (unsigned)(x * sizeof(T));
-      pc.ym = y > 0 ? y - 1 : p.ny - 1;
-      pc.yp = y < p.ny - 1 ? y + 1 : 0;
+      // (readfirstlane: the compiler then keeps the row arithmetic, and
+      // the row bases of all accesses, in scalar registers)
+      pc.ym = __builtin_amdgcn_readfirstlane(y > 0 ? y - 1 : p.ny - 1);
+      pc.yp = __builtin_amdgcn_readfirstlane(y < p.ny - 1 ? y + 1 : 0);
       ka_cell<T, INIT, MRT, true>(p, B, dphi, mupl, lam_in, x, y, o, th, pc);
-      const long long r = (long long)y * p.nx;
+      const long long r = (long long)__builtin_amdgcn_readfirstlane(y) * p.nx;
 #pragma unroll
       for (int i = 0; i < 9; ++i) st_at<false>(lam_out + (9 + i) * n + r, pc.bc, o.lg[i]);
       st_at<false>(lam_out + 18 * n + r, pc.bc, o.lS);
@@ -670,8 +674,9 @@ __global__ __launch_bounds__(KM_THREADS) void ka_mu_phi(const KP p, const T* __r
     const unsigned cb[3] = {(unsigned)(pre1(xc, 1, p.nx) * sizeof(C)), (unsigned)(xc * sizeof(C)),
                             (unsigned)(pre1(xc, -1, p.nx) * sizeof(C))};  // x - 1, x, x + 1
     auto load_row = [&](int ty, RowIn& in) {
-      const int y = min(y0 + ty, p.ny - 1);
-      const int ys[3] = {pre1(y, 1, p.ny), y, pre1(y, -1, p.ny)};  // y - 1, y, y + 1
+      const int y = __builtin_amdgcn_readfirstlane(min(y0 + ty, p.ny - 1));
+      const int ys[3] = {__builtin_amdgcn_readfirstlane(pre1(y, 1, p.ny)), y,
+                         __builtin_amdgcn_readfirstlane(pre1(y, -1, p.ny))};  // y - 1, y, y + 1
 #pragma unroll
       for (int a = 0; a < 3; ++a)
 #pragma unroll
