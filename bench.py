@@ -40,8 +40,9 @@ STEP_BYTES = {32: 2 * 19 * 4, 64: 2 * 19 * 8}
 # of the rest population of f (read and written) that keeps f_0 to about
 # 2^-40; phi and mu stay on chip.
 STEP_IMPL_BYTES = {32: 2 * (18 * 4 + 2 + 4), 64: STEP_BYTES[64]}
-# Two steps per launch: the state read and written once per two steps.
-TWO_STEP_IMPL_BYTES = {32: STEP_IMPL_BYTES[32] / 2}
+# Two steps per launch: the state read and written once per two steps (with
+# the 32-bit low word of f_0, which the library keeps on that path).
+TWO_STEP_IMPL_BYTES = {32: (18 * 4 + 4 + 4) * 2 / 2}
 # The two-kernel design: the phi/mu pass also reads the 9 f planes and writes
 # phi and mu, and the collide pass reads them back: +(9 + 2 + 2) planes.
 TWO_KERNEL_BYTES = {32: STEP_BYTES[32] + (9 + 2 + 2) * 4, 64: STEP_BYTES[64] + (9 + 2 + 2) * 8}

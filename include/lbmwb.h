@@ -137,8 +137,10 @@ enum { LBM_LO_AUTO = 0, LBM_LO_16 = 1, LBM_LO_32 = 2 };
  *                  is the BGK step.
  *   lo_format      FP32 only (ignored for precision 64): the storage of the
  *                  low word lo of the rest population's pair hi + lo.
- *                  LBM_LO_AUTO: 16 bits for states above 1 GiB (where the
- *                  step is bound by HBM traffic), an FP32 word below;
+ *                  LBM_LO_AUTO: 16 bits for states above 1 GiB that run
+ *                  one step per launch (where the step is bound by HBM
+ *                  traffic), an FP32 word below and with two steps per
+ *                  launch (lbm_derived.two_step);
  *                  LBM_LO_16: always the 16-bit fraction of ulp(hi);
  *                  LBM_LO_32: always an FP32 word.  The state size does not
  *                  depend on it.

@@ -226,13 +226,18 @@ constexpr long long FUSED_FEW_ROUNDS = 4;
 // is not hidden
 constexpr size_t LO16_STATE_BYTES = (size_t)1 << 30;
 
+bool two_step_of(const lbm_params* p, size_t state_bytes);
+
 // FP32: the low word of f_0 in 16 bits (lbm_params.lo_format; automatic:
-// for states above LO16_STATE_BYTES, where the 16-bit word pays)
+// for states above LO16_STATE_BYTES that the one-step kernels run, where
+// the step is bound by HBM and the 16-bit word pays; the two-step kernel is
+// bound by instruction latency instead, and keeps the 32-bit word: 16384^2
+// on MI355X, 5.00 against 5.45 ms per step)
 bool lo16_of(const lbm_params* p, size_t state_bytes) {
   if (p->precision != 32) return false;
   if (p->lo_format == LBM_LO_16) return true;
   if (p->lo_format == LBM_LO_32) return false;
-  return state_bytes > LO16_STATE_BYTES;
+  return state_bytes > LO16_STATE_BYTES && !two_step_of(p, state_bytes);
 }
 
 // Two steps per launch (k_step2): asked for (kernel_path 3), or automatic

@@ -135,12 +135,16 @@ def test_derive_rejects_relaxation_times(bad):
     assert _derive(make_params(inputs.DROPLET, **kw))[0] == _lib.LBM_EINVAL
 
 
-@pytest.mark.parametrize("prec,fmt,n,want", [
-    (32, _lib.LO_AUTO, 512, 0), (32, _lib.LO_AUTO, 8192, 1), (32, _lib.LO_16, 512, 1),
-    (32, _lib.LO_32, 8192, 0), (64, _lib.LO_16, 512, 0)])
-def test_low_word_format(prec, fmt, n, want):
+@pytest.mark.parametrize("prec,fmt,n,path,want", [
+    (32, _lib.LO_AUTO, 512, 0, 0), (32, _lib.LO_AUTO, 8192, 2, 1), (32, _lib.LO_AUTO, 8192, 0, 0),
+    (32, _lib.LO_AUTO, 8192, 3, 0), (32, _lib.LO_16, 512, 0, 1), (32, _lib.LO_16, 8192, 0, 1),
+    (32, _lib.LO_32, 8192, 2, 0), (64, _lib.LO_16, 512, 0, 0)])
+def test_low_word_format(prec, fmt, n, path, want):
     # automatic: 16 bits above a 1 GiB state (512^2 FP32 is 41 MiB, 8192^2 10 GiB)
-    rc, d = _derive(make_params(inputs.THROUGHPUT, precision=prec, nx=n, ny=n, lo_format=fmt))
+    # for the one-step kernels; two steps per launch (automatic here on the
+    # periodic 8192^2 grid) keep the 32-bit word
+    rc, d = _derive(make_params(inputs.THROUGHPUT, precision=prec, nx=n, ny=n, lo_format=fmt,
+                                kernel_path=path))
     assert rc == 0 and d.lo16 == want
 
 
