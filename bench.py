@@ -157,6 +157,10 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
         # calibrated) over the same live launch time
         "measured_bytes_frac": None if traffic is None
         else round(traffic / (launch_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS, 4),
+        # the same counted bytes per cell update (two steps per launch: the
+        # state is read and written once for two updates)
+        "counted_bytes_per_cell_update": None if traffic is None
+        else round(traffic / ((per_launch if kernel_path != 1 else 1) * ncell), 1),
         "diag_after": {k: d[k] for k in ("sum_phi", "max_u", "min_rho", "n_nonfinite", "step")},
     }
 
@@ -495,6 +499,7 @@ def main():
         },
         "roofline": r32["roofline"],
         "measured_bytes_frac": r32["measured_bytes_frac"],
+        "counted_bytes_per_cell_update": r32["counted_bytes_per_cell_update"],
         "steps_per_launch": r32["steps_per_launch"],
         "cpu_baseline": cpu,
         "error_vs_oracle": err,
