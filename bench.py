@@ -66,8 +66,9 @@ def kernel_source_hash() -> str:
 
 
 def measured_traffic(key: str):
-    """HBM bytes per launch of a step kernel ("two_step_32": two steps; "32",
-    "64": one step), or per step of the two-kernel path ("two_kernel_32"),
+    """HBM bytes per launch of a step kernel ("two_step_32": two steps,
+    "two_step_32_mrt" with the MRT collision; "32", "64": one step), or per
+    step of the two-kernel path ("two_kernel_32"),
     from the committed rocprofv3 counter summary, if it was taken on the
     current kernel source."""
     try:
@@ -134,7 +135,8 @@ def run_gpu(phi0_dev, prec: int, steps: int, warmup: int, kernel_steps: int, wl,
     # algorithmic bytes per launch (steps per launch x cells x bytes per
     # cell update) over the launch's duration
     ach = alg * ncell / (avg * 1e-3) / 1e9
-    traffic = None if mrt else measured_traffic(key)
+    # counters were taken for the MRT collision on the two-step path only
+    traffic = measured_traffic(key + "_mrt" if per_launch == 2 else "") if mrt else measured_traffic(key)
     launch_ms = avg * (per_launch if kernel_path != 1 else 1)
     return {
         "mlups": ncell * steps / (ms * 1e-3) / 1e6,

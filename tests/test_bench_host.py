@@ -33,6 +33,12 @@ def test_traffic_record_is_consistent():
         alg = bench.STEP_IMPL_BYTES[int(key)] * 16384 * 16384 // 2
         assert r["algorithmic_read_bytes"] == r["algorithmic_write_bytes"] == alg
     assert bench.measured_traffic("two_kernel_32") == rec["two_kernel_32"]["bytes_per_step"]
+    # two steps per launch: one read and one write of the state per launch
+    for key in ("two_step_32", "two_step_32_mrt"):
+        r = rec[key]
+        assert bench.measured_traffic(key) == r["bytes_per_launch"] == r["fetch_bytes"] + r["write_bytes"]
+        alg = bench.TWO_STEP_IMPL_BYTES[32] * 16384 * 16384
+        assert r["algorithmic_read_bytes"] == r["algorithmic_write_bytes"] == alg
 
 
 def test_traffic_withheld_for_other_sources(tmp_path, monkeypatch):

@@ -1,8 +1,8 @@
 """lbm_step_noalloc: the step for callers that cannot allocate, with its
 diagnostic reductions in the library's per-GPU scratch, against lbm_step on
-twin contexts, bit for bit (same kernels, same reduction order): two calls in
-a row on different contexts, the second on a smaller grid, so the second
-reuses the scratch the first left behind."""
+twin contexts, bit for bit (same kernels, same reduction order): three calls
+in a row on different contexts, each on a smaller grid than the one before,
+so that each reuses the scratch the one before left behind."""
 import sys
 
 import numpy as np
@@ -18,24 +18,26 @@ def say(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-# (nx, ny, precision, kernel_path): the fused step, then the two-kernel step
-# on a smaller grid
-CALLS = [(300, 200, 64, 2), (130, 70, 32, 1)]
+# (nx, ny, precision, kernel_path, diag_every): the fused step, then the
+# two-kernel step on a smaller grid, then two steps per launch on a smaller
+# one still (diagnostics every 5 steps: steps 1-4 run as two launches of two
+# steps each)
+CALLS = [(300, 200, 64, 2, 2), (130, 70, 32, 1, 2), (120, 64, 32, 3, 5)]
 
 
 def test_step_noalloc_matches_step():
     wl = inputs.COALESCENCE
-    for nx, ny, prec, path in CALLS:
+    for nx, ny, prec, path, every in CALLS:
         say(f"[gpu] lbm_step_noalloc vs lbm_step: {nx}x{ny} fp{prec} kernel_path={path}")
         phi0 = inputs.two_drops(nx, ny, 0.15 * nx, 5.0, noise=1e-3, workload_id=3)
-        ref = gpu_sim(wl, phi0, prec, diag_every=2, nx=nx, ny=ny, kernel_path=path)
-        new = gpu_sim(wl, phi0, prec, diag_every=2, nx=nx, ny=ny, kernel_path=path)
+        ref = gpu_sim(wl, phi0, prec, diag_every=every, nx=nx, ny=ny, kernel_path=path)
+        new = gpu_sim(wl, phi0, prec, diag_every=every, nx=nx, ny=ny, kernel_path=path)
         ref.step(7)
         new.step_noalloc(7)
         for a, b in zip(gpu_state(ref), gpu_state(new)):
             assert np.array_equal(a, b)
         da, db = ref.last_diag(), new.last_diag()
-        assert da["ok"] and db["ok"] and da["step"] == db["step"] == 6
+        assert da["ok"] and db["ok"] and da["step"] == db["step"] == 6 // every * every
         assert da == db
         assert new.step_count == ref.step_count == 7
         ref.close()
