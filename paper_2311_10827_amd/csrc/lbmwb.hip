@@ -207,12 +207,12 @@ constexpr size_t FUSED_CACHED_STATE_BYTES = (size_t)224 << 20;
 // 4096^2 and 3 % at 1024^2 in FP32, and 1.5-3 % slower at 16384^2 in FP64
 constexpr long long FUSED_DISPATCH_ORDER_BLOCKS_32 = 8192;
 // k_step2 launches aim at no fewer workgroups than this (two rounds of two
-// per CU): at 4096^2, 64-row strips (1216 workgroups) take 0.481 ms per
-// step on MI355X, 32-row strips 0.489 ms and 128-row strips (608) 0.589 ms;
-// at 16384^2 the 128-row strips are 3 % faster than 64-row ones
+// per CU): at 4096^2 on MI355X, 128-row strips (608 workgroups) were a fifth
+// slower than 64-row ones; at 16384^2 the 128-row strips are 3 % faster than
+// 64-row ones
 constexpr long long S2_MIN_BLOCKS = 1024;
-// k_step2: resident workgroups per CU (its ~200 VGPRs), and the lowest
-// strip height the round-filling choice considers
+// k_step2: resident workgroups per CU (its 175 VGPRs and 74 KB of LDS), and
+// the lowest strip height the round-filling choice considers
 constexpr int S2_WG_PER_CU = 2;
 constexpr int S2_ROUND_H_MIN = 48;
 // FP32 fused step: resident workgroups per CU (its 48 KB of LDS), and the
@@ -242,10 +242,9 @@ bool lo16_of(const lbm_params* p, size_t state_bytes) {
 
 // Two steps per launch (k_step2): asked for (kernel_path 3), or automatic
 // for FP32 states on periodic grids beyond the last-level cache (measured on
-// MI355X, against the fused single step: 16384^2 5.92 against 7.50 ms per
-// step, 8192^2 1.93 against 2.11, 4096^2 0.461 against 0.533, 2048^2 equal;
-// at 1024^2, where the single step runs from the cache, 0.050 against
-// 0.039 ms)
+// MI355X, against the fused single step: 16384^2 4.60 against 7.49 ms per
+// step, 4096^2 0.31 against 0.53, 2048^2 0.114 against 0.15; at 1024^2,
+// where the single step runs from the cache, 0.040 against 0.036 ms)
 bool two_step_of(const lbm_params* p, size_t state_bytes) {
   if (p->kernel_path == 3) return true;
   return p->kernel_path == 0 && p->precision == 32 && p->bc_x == 0 && p->bc_y == 0 &&
