@@ -46,10 +46,16 @@ def _case(name):
     if name == "one_column":
         phi0 = np.ascontiguousarray(np.tanh((np.arange(70.0)[:, None] - 35.0) / 2.0))
         return inputs.FLAT, phi0, dict(nx=1, ny=70, bc_x=1, bc_y=1)
+    if name == "one_row_periodic":
+        # a slab of phase A across a periodic row: every row neighbour, and
+        # every stencil row beyond it, wraps onto the one row
+        phi0 = np.ascontiguousarray(-np.tanh((np.abs(np.arange(70.0) - 35.0) - 17.0) / 2.0)[None, :])
+        return inputs.FLAT, phi0, dict(nx=70, ny=1, bc_x=0, bc_y=0)
     raise KeyError(name)
 
 
-CASES = ["flat", "drop64", "ragged_walls", "ragged_periodic", "tiny_periodic", "tiny_walls", "one_column"]
+CASES = ["flat", "drop64", "ragged_walls", "ragged_periodic", "tiny_periodic", "tiny_walls", "one_column",
+         "one_row_periodic"]
 
 
 # kernel_path 1: phi/mu pass + collide pass; 2: the fused step kernel

@@ -48,7 +48,7 @@ def _pair(nx, ny, n, **over):
     return a, b
 
 
-@pytest.mark.parametrize("shape", [(300, 200), (224, 128), (3, 5), (1, 70), (450, 9), (1000, 700)])
+@pytest.mark.parametrize("shape", [(300, 200), (224, 128), (3, 5), (1, 70), (70, 1), (450, 9), (1000, 700)])
 @pytest.mark.parametrize("n", [1, 2, 7, 40])
 def test_two_step_matches_single_steps_bitwise(shape, n):
     nx, ny = shape
