@@ -343,18 +343,24 @@ def adjoint_leg(nsteps: int, K: int, n: int = 0):
     # is the reference.  The rollout (and so its checkpoint recompute, which
     # writes every state to a snapshot of its own) runs the fused kernel,
     # which writes fewer bytes per recomputed state.
-    t_fwd = {}
+    # Both parts of the ratio are the median of three timed runs (each run
+    # varies by 1-2 % from the next).
+    import statistics
+    t_fwd, runs_fwd = {}, {}
     for kp in (2, 1, 3):
         base.kernel_path = kp
         sim = Sim(params_from_theta(base, theta), phi0)
         sim.step(20)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(sim.stream)
-        sim.step(nsteps)
-        e1.record(sim.stream)
-        torch.cuda.synchronize()
-        t_fwd[kp] = e0.elapsed_time(e1) / nsteps
+        runs = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(sim.stream)
+            sim.step(nsteps)
+            e1.record(sim.stream)
+            torch.cuda.synchronize()
+            runs.append(e0.elapsed_time(e1) / nsteps)
+        t_fwd[kp], runs_fwd[kp] = statistics.median(runs), runs
         sim.close()
         del sim
     kp_best = min(t_fwd, key=t_fwd.get)
@@ -362,14 +368,17 @@ def adjoint_leg(nsteps: int, K: int, n: int = 0):
     log(f"[bench] adjoint: forward ms/step fused {t_fwd[2]:.4f}, two-kernel {t_fwd[1]:.4f}, "
         f"two steps per launch {t_fwd[3]:.4f}")
     log(f"[bench] adjoint: rollout {nsteps} steps, checkpoint every {K} (one warm-up gradient, "
-        "then the timed one: buffers come from torch's caching allocator)")
-    for _ in range(2):
+        "then three timed ones: buffers come from torch's caching allocator)")
+    runs_bwd = []
+    for i in range(4):
         ph = torch.from_numpy(phi0).cuda().requires_grad_(True)
         th = torch.tensor(theta, dtype=torch.float64, requires_grad=True)
         stats = {}
         L = misfit(rollout(ph, th, base, nsteps, K, stats), tgt)
         L.backward()
-    t_bwd = stats["backward_s"] * 1e3 / nsteps
+        if i:
+            runs_bwd.append(stats["backward_s"] * 1e3 / nsteps)
+    t_bwd = statistics.median(runs_bwd)
     return {
         "workload": f"{wl.name}: {wl.nx}x{wl.ny} two drops R {wl.extra['R']:g}, density ratio 100, FP32, "
                     f"{nsteps} steps, checkpoint every {K}",
@@ -381,6 +390,8 @@ def adjoint_leg(nsteps: int, K: int, n: int = 0):
         "rollout_step_form": "fused",
         "adjoint_ms_per_step_incl_recompute": round(t_bwd, 5),
         "ratio": round(t_bwd / t_fwd[kp_best], 3),
+        "runs_ms_per_step": {"forward": [round(t, 5) for t in runs_fwd[kp_best]],
+                             "adjoint": [round(t, 5) for t in runs_bwd]},
         "loss": float(L.detach()),
         "dL_dtheta": dict(zip(("kappa", "beta", "M", "tau_f", "tau_gA", "tau_gB"),
                               [float(v) for v in th.grad])),
