@@ -166,9 +166,10 @@ def test_dot_product_segment_periodic():
     assert abs(lhs - rhs) <= 1e-12 * max(abs(lhs), 1e-300)
 
 
+@pytest.mark.parametrize("walls", [0, 1])
 @pytest.mark.parametrize("collision", ["bgk", "mrt"])
 @pytest.mark.parametrize("prec", [64, 32])
-def test_segment_equals_single_steps(prec, collision):
+def test_segment_equals_single_steps(prec, collision, walls):
     # lbm_adjoint_segment against its recompute and adjoint steps made one
     # call at a time: FP64 to 1e-13 and FP32 to 1e-5 of the largest entry,
     # the parameter gradient to 1e-12 and 1e-4 of its largest entry (the same
@@ -177,8 +178,8 @@ def test_segment_equals_single_steps(prec, collision):
     nx, ny, n = 70, 45, 7
     over = dict(collision=MRT, mrt_f=(1.3, 1.1, 1.6, 1.4), mrt_g=(1.5, 1.7)) if collision == "mrt" else {}
     phi0 = inputs.two_drops(nx, ny, 10.0, 4.0, noise=1e-3, workload_id=5)
-    say(f"[gpu] adjoint segment vs single steps, {nx}x{ny} fp{prec} {collision}, {n} steps")
-    sim = gpu_sim(inputs.ADJOINT, phi0, prec, nx=nx, ny=ny, **over)
+    say(f"[gpu] adjoint segment vs single steps, {nx}x{ny} fp{prec} {collision} walls={walls}, {n} steps")
+    sim = gpu_sim(inputs.ADJOINT, phi0, prec, nx=nx, ny=ny, bc_x=walls, bc_y=walls, **over)
     sim.step(3)
     sim.enable_adjoint()
     s0 = sim.snapshot()
