@@ -144,23 +144,25 @@ def test_coalescence_crop_10000_steps():
     # 1e-5 in phi and 1e-6 in u of the FP64 oracle, with the rest
     # population's low word in either format (the automatic choice keeps it
     # in an FP32 word at this size; the 16-bit word is what the large
-    # benchmark states run with)
+    # one-step states run with), and in FP32 two steps per launch (the form
+    # the large periodic FP32 states run)
     from paper_2311_10827_amd import _lib
     from paper_2311_10827_amd.sim import derive, make_params
     wl, phi0, over = _crop()
     say("[gpu] coalescence crop, 10000 steps: oracle (about a minute on the host)")
     o = oracle_sim(wl, phi0, **over).step(10000)
     ostate, om = o.get_state(), o.moments()
-    for prec, fmt in ((64, _lib.LO_AUTO), (32, _lib.LO_AUTO), (32, _lib.LO_16)):
-        lo16 = derive(make_params(wl, precision=prec, lo_format=fmt, **over))["lo16"]
+    for prec, fmt, path in ((64, _lib.LO_AUTO, 0), (32, _lib.LO_AUTO, 0), (32, _lib.LO_16, 0),
+                            (32, _lib.LO_AUTO, 3)):
+        lo16 = derive(make_params(wl, precision=prec, lo_format=fmt, kernel_path=path, **over))["lo16"]
         assert lo16 == (fmt == _lib.LO_16)
-        g = gpu_sim(wl, phi0, prec, lo_format=fmt, **over)
+        g = gpu_sim(wl, phi0, prec, lo_format=fmt, kernel_path=path, **over)
         g.step(10000)
         gm, d = gpu_moments(g)
         assert d["n_nonfinite"] == 0
         e_phi = np.abs(gm["phi"] - om["phi"]).max()
         e_u = max(np.abs(gm["ux"] - om["ux"]).max(), np.abs(gm["uy"] - om["uy"]).max())
-        say(f"  fp{prec} (16-bit low word: {lo16}): phi err {e_phi:.3e}  u err {e_u:.3e}  "
+        say(f"  fp{prec} kernel_path {path} (16-bit low word: {lo16}): phi err {e_phi:.3e}  u err {e_u:.3e}  "
             f"max|u| {np.hypot(om['ux'], om['uy']).max():.3e}")
         if prec == 64:
             compare_state(gpu_state(g), ostate, TOL64)
