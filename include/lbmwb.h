@@ -256,8 +256,8 @@ int lbm_init(lbm_ctx** out, const lbm_params* p, void* state, void* workspace,
  * eq. order-parameter) and mu (eq. chemical_potencial with the isotropic
  * Laplacian of Sec. 2.3.2, eq. Laplace), then collides and pull-streams both
  * populations (Sec. 2.3.1, eq. BGK; Sec. 2.3.2, eqs. BGK-NS, G_i, Siu, GGi
- * and the u, p recovery), in one kernel or two (kernel_path).
- * Asynchronous.  With diag_every = k > 0 every k-th step also reduces the
+ * and the u, p recovery), in one kernel or two, or two steps in one kernel
+ * (kernel_path).  Asynchronous.  With diag_every = k > 0 every k-th step also reduces the
  * diagnostics of its pre-collision state; a pass that found a non-finite
  * value or rho <= 0 makes a later lbm_step (or lbm_last_diag) return
  * LBM_ENONFINITE once that pass has completed on the device.
